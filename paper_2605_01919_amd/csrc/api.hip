@@ -1,0 +1,95 @@
+// Library-wide entry points: options, errors, version, workspace sizes.
+#include "common.h"
+
+#include <cstring>
+
+namespace sdfi {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+sdfi_status read_options(const sdfi_options *opt, sdfi_options *out) {
+    sdfi_default_options(out);
+    if (!opt) return SDFI_OK;
+    if (opt->struct_size != sizeof(sdfi_options)) {
+        set_error("sdfi_options.struct_size is %u, expected %zu", opt->struct_size, sizeof(sdfi_options));
+        return SDFI_ERR_INVALID_ARGUMENT;
+    }
+    *out = *opt;
+    if (out->precision != SDFI_PREC_FP64 && out->precision != SDFI_PREC_FP32_FP64_RECHECK) {
+        set_error("unknown precision %d", out->precision);
+        return SDFI_ERR_INVALID_ARGUMENT;
+    }
+    if (!(out->tol >= 0.0) || !(out->tie_tol >= 0.0)) {
+        set_error("tolerances must be non-negative");
+        return SDFI_ERR_INVALID_ARGUMENT;
+    }
+    if (out->grid < 0 || out->grid > 1024) {
+        set_error("grid must be in [0, 1024], got %d", out->grid);
+        return SDFI_ERR_INVALID_ARGUMENT;
+    }
+    if (out->block_size != 0 && out->block_size != 256 && out->block_size != 512 && out->block_size != 1024) {
+        set_error("block_size must be 0, 256, 512 or 1024, got %d", out->block_size);
+        return SDFI_ERR_INVALID_ARGUMENT;
+    }
+    for (int k = 0; k < 3; ++k) {
+        if (!(out->domain_lo[k] < out->domain_hi[k])) {
+            set_error("empty domain box on axis %d", k);
+            return SDFI_ERR_INVALID_ARGUMENT;
+        }
+    }
+    return SDFI_OK;
+}
+
+}  // namespace sdfi
+
+extern "C" {
+
+void sdfi_default_options(sdfi_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->struct_size = sizeof(sdfi_options);
+    o->precision = SDFI_PREC_FP32_FP64_RECHECK;
+    o->tol = 1e-6;
+    o->tie_tol = 1e-9;
+    for (int k = 0; k < 3; ++k) {
+        o->domain_lo[k] = -1.0;
+        o->domain_hi[k] = 1.0;
+    }
+    o->grid = 0;
+    o->block_size = 0;
+    o->flags = 0;
+}
+
+const char *sdfi_last_error(void) { return sdfi::g_err; }
+
+const char *sdfi_version(void) { return "sdfi 0.1 gfx950"; }
+
+sdfi_status sdfi_workspace_size(sdfi_op op, int64_t n, int64_t m, const sdfi_options *opt, size_t *bytes) {
+    using namespace sdfi;
+    sdfi_options o;
+    sdfi_status s = read_options(opt, &o);
+    if (s != SDFI_OK) return s;
+    SDFI_CHECK_ARG(bytes != nullptr, "bytes is null");
+    SDFI_CHECK_ARG(n >= 0 && m >= 0, "negative size");
+    switch (op) {
+    case SDFI_OP_BOUNDS: *bytes = bounds_ws(n > 0 ? n : 1, m, o); break;
+    case SDFI_OP_CERTIFY: *bytes = certify_ws(n, o); break;
+    case SDFI_OP_ORDER: *bytes = order_ws(n, m, o); break;
+    case SDFI_OP_WITNESS: *bytes = witness_ws(n, o); break;
+    case SDFI_OP_GREEDY: *bytes = greedy_ws(n, m, o); break;
+    case SDFI_OP_RMIN: *bytes = rmin_ws(n, m, o); break;
+    case SDFI_OP_REPAIR: *bytes = repair_ws(n, m, o); break;
+    case SDFI_OP_BACKWARD: *bytes = backward_ws(n, m); break;
+    default: set_error("unknown op %d", (int)op); return SDFI_ERR_INVALID_ARGUMENT;
+    }
+    return SDFI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,75 @@
+// Host-side helpers shared by the sdfi entry points: status/error handling,
+// option validation and workspace carving.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/sdfi.h"
+
+namespace sdfi {
+
+void set_error(const char *fmt, ...);
+
+#define SDFI_CHECK_ARG(cond, ...)                 \
+    do {                                          \
+        if (!(cond)) {                            \
+            ::sdfi::set_error(__VA_ARGS__);       \
+            return SDFI_ERR_INVALID_ARGUMENT;     \
+        }                                         \
+    } while (0)
+
+#define SDFI_HIP(call)                                                          \
+    do {                                                                        \
+        hipError_t e_ = (call);                                                 \
+        if (e_ != hipSuccess) {                                                 \
+            ::sdfi::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, __LINE__); \
+            return SDFI_ERR_DEVICE;                                             \
+        }                                                                       \
+    } while (0)
+
+// Validated copy of the caller's options (defaults when opt == NULL).
+sdfi_status read_options(const sdfi_options *opt, sdfi_options *out);
+
+// Bump allocator over the caller's workspace; every carve is 256-byte aligned.
+struct Carver {
+    char *base;
+    size_t cap;
+    size_t used = 0;
+    bool dry;  // sizing pass: base may be null
+    Carver(void *b, size_t c, bool d = false) : base(static_cast<char *>(b)), cap(c), dry(d) {}
+    template <typename T>
+    T *take(size_t count) {
+        size_t off = (used + 255) & ~size_t(255);
+        used = off + count * sizeof(T);
+        if (dry) return nullptr;
+        return reinterpret_cast<T *>(base + off);
+    }
+    bool ok() const { return dry || used <= cap; }
+};
+
+inline hipStream_t to_hip(sdfi_stream s) { return reinterpret_cast<hipStream_t>(s); }
+
+// workspace sizes per operation (defined next to each operation)
+size_t bounds_ws(int64_t n, int64_t m, const sdfi_options &o);
+size_t certify_ws(int64_t N, const sdfi_options &o);
+size_t order_ws(int64_t n, int64_t m, const sdfi_options &o);
+size_t witness_ws(int64_t n, const sdfi_options &o);
+size_t greedy_ws(int64_t n, int64_t m, const sdfi_options &o);
+size_t rmin_ws(int64_t n, int64_t m, const sdfi_options &o);
+size_t repair_ws(int64_t n, int64_t m, const sdfi_options &o);
+size_t backward_ws(int64_t n, int64_t m);
+
+// dense bound sweep used by sdfi_bounds and internally (samples n x 4)
+sdfi_status run_bounds(const double *samples, int64_t n, const double *queries, int64_t m, double *lo,
+                       double *hi, int32_t *argmax, int32_t *argmin, uint32_t *flags, Carver &ws,
+                       const sdfi_options &o, hipStream_t st, int64_t *overflow_count);
+
+sdfi_status run_certify(const double *pv, const double *wit, int64_t N, int64_t *pair_viol, int64_t *wit_viol,
+                        Carver &ws, const sdfi_options &o, hipStream_t st);
+
+}  // namespace sdfi

@@ -1,0 +1,67 @@
+"""The C ABI library loads and exports every entry point of include/sdfi.h;
+argument errors are caught on the host (no GPU needed)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2605_01919_amd import sdfi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "sdfi.h")).read()
+    return sorted(set(re.findall(r"\b(sdfi_[a-z_]+)\s*\(", text)))
+
+
+def test_header_matches_binding_list():
+    assert header_functions() == sorted(sdfi.EXPORTS)
+
+
+def test_library_exports_every_symbol():
+    out = subprocess.check_output(["nm", "-D", "--defined-only", sdfi.LIB_PATH]).decode()
+    exported = set(re.findall(r" T (sdfi_\w+)", out))
+    missing = [f for f in header_functions() if f not in exported]
+    assert not missing, missing
+    for f in header_functions():
+        getattr(sdfi.lib(), f)
+
+
+def test_defaults_and_version():
+    o = sdfi.options()
+    assert o.tol == 1e-6 and o.tie_tol == 1e-9 and o.struct_size == ctypes.sizeof(sdfi.Options)
+    assert b"gfx950" in sdfi.lib().sdfi_version()
+
+
+def test_argument_errors_on_host():
+    L = sdfi.lib()
+    o = sdfi.options()
+    st = L.sdfi_bounds(None, ctypes.c_int64(10), None, ctypes.c_int64(5), None, None, None, None, None, None,
+                       ctypes.c_size_t(0), ctypes.byref(o), None)
+    assert st == 1 and b"null" in L.sdfi_last_error()
+    st = L.sdfi_bounds(None, ctypes.c_int64(0), None, ctypes.c_int64(5), None, None, None, None, None, None,
+                       ctypes.c_size_t(0), ctypes.byref(o), None)
+    assert st == 1
+    bad = sdfi.options()
+    bad.struct_size = 3
+    size = ctypes.c_size_t()
+    assert L.sdfi_workspace_size(0, 10, 10, ctypes.byref(bad), ctypes.byref(size)) == 1
+    bad = sdfi.options()
+    bad.precision = 7
+    assert L.sdfi_workspace_size(0, 10, 10, ctypes.byref(bad), ctypes.byref(size)) == 1
+    rep = sdfi.Report()
+    assert L.sdfi_certify(None, None, ctypes.c_int64(4), ctypes.byref(rep), None, ctypes.c_size_t(0),
+                          ctypes.byref(o), None) == 1
+
+
+def test_workspace_sizes_grow():
+    o = sdfi.options()
+    s1, s2 = ctypes.c_size_t(), ctypes.c_size_t()
+    L = sdfi.lib()
+    for op in range(8):
+        assert L.sdfi_workspace_size(op, 100, 100, ctypes.byref(o), ctypes.byref(s1)) == 0
+        assert L.sdfi_workspace_size(op, 10000, 10000, ctypes.byref(o), ctypes.byref(s2)) == 0
+        assert s2.value >= s1.value > 0

@@ -1,0 +1,117 @@
+"""GPU parity of sdfi_bounds and sdfi_certify against the oracle (Sec. 4.3 bounds; Prop. 1)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import bounds as OB
+from oracle import greedy as OG
+from oracle.common import TOL, dist
+from paper_2605_01919_amd import sdfi
+from sdfgen import configs
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def run(P, S, Q, prec):
+    out = sdfi.bounds(dev(np.c_[P, S]), dev(Q), prec)
+    torch.cuda.synchronize()
+    return [t.cpu().numpy() for t in out]
+
+
+def check_full(P, S, Q, prec):
+    lo, hi, a, b, f = run(P, S, Q, prec)
+    olo, ohi, oa, ob, of = OB.cone_bounds(P, S, Q)
+    np.testing.assert_allclose(lo, olo, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(hi, ohi, rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(a, oa)
+    np.testing.assert_array_equal(b, ob)
+    np.testing.assert_array_equal(f.astype(np.uint32), of)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("case", ["sphere6", "balls8", "ragged", "single", "constant", "box"])
+def test_bounds_full_parity(prec, case):
+    rng = np.random.default_rng(11)
+    if case == "sphere6":
+        w = configs.sphere(6)
+        P, S, Q = w.points, w.values, w.queries
+    elif case == "balls8":
+        w = configs.ball_union(8)
+        P, S, Q = w.points, w.values, w.queries
+    elif case == "ragged":      # several tiles plus a ragged tail on both axes
+        P = rng.uniform(0, 1, (1000, 3)); S = rng.uniform(-0.3, 0.3, 1000); Q = rng.uniform(0, 1, (777, 3))
+    elif case == "single":
+        P = np.array([[0.3, 0.4, 0.5]]); S = np.array([0.1]); Q = rng.uniform(0, 1, (300, 3))
+    elif case == "constant":    # every sample ties: exercises the tie band and list overflow
+        P = configs.grid_centres(8); S = np.full(512, 0.05); Q = configs.grid_centres(4)
+    else:
+        from sdfgen import shapes
+        P = configs.grid_centres(10); S = shapes.box_sdf(P, (0.5, 0.5, 0.5), (0.2, 0.3, 0.25))
+        Q = configs.grid_centres(20)
+    print(f"bounds parity {case} {prec} n={len(S)} m={len(Q)}", flush=True)
+    check_full(P, S, Q, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_bounds_sphere16_full(prec):
+    w = configs.sphere(16)
+    print("bounds sphere16 full", prec, flush=True)
+    check_full(w.points, w.values, w.queries, prec)
+
+
+def test_bounds_balls64_sampled():
+    # full 64^3 x 128^3 sweep in the benchmark's configuration; 400 sampled
+    # queries recomputed one by one by the oracle
+    w = configs.by_name("balls64")
+    print("bounds balls64 full size", flush=True)
+    lo, hi, a, b, f = run(w.points, w.values, w.queries, "fp32")
+    idx = np.random.default_rng(2002).choice(w.m, 400, replace=False)
+    for j in idx:
+        l, h, aa, bb, _ = OB.bounds_one(w.queries[j], w.points, w.values)
+        assert abs(lo[j] - l) <= 1e-12 and abs(hi[j] - h) <= 1e-12
+        assert a[j] == aa and b[j] == bb
+    # 1-Lipschitz property at any size: the exact SDF lies in [lo, hi]
+    from sdfgen import shapes
+    phi = shapes.ball_union_sdf(w.queries[idx], w.meta["centres"], w.meta["radii"])
+    assert np.all(lo[idx] <= phi + 1e-12) and np.all(phi <= hi[idx] + 1e-12)
+
+
+def test_bounds_empty_queries():
+    out = sdfi.bounds(dev(np.array([[0.1, 0.2, 0.3, 0.1]])), torch.zeros((0, 3), dtype=torch.float64, device="cuda"))
+    assert out[0].numel() == 0
+
+
+def oracle_cert_rows(P, S, W):
+    R = np.abs(S)
+    N = len(S)
+    npair = 0
+    wit = np.zeros(N, dtype=bool)
+    for i in range(N):
+        d = dist(P, P[i])
+        npair += int(np.sum((np.abs(S - S[i]) > d + TOL) & (np.arange(N) > i)))
+        dw = dist(P, W[i])
+        cov = dw < R - TOL - 1e-9
+        cov[i] = False
+        off = not (abs(dist(W[i], P[i]) - R[i]) <= TOL)
+        wit[i] = cov.any() or off
+    return npair, int(wit.sum())
+
+
+def test_certify_parity_with_planted_violations():
+    w = configs.sphere(8)
+    W, ok = OG.input_witnesses(w.points, w.values)
+    S = w.values.copy()
+    rng = np.random.default_rng(3)
+    bump = rng.choice(len(S), 12, replace=False)
+    S[bump] += rng.uniform(0.01, 0.1, 12)       # breaks cones and covers neighbours' witnesses
+    W2 = W.copy()
+    W2[5] = np.nan
+    for Sx, Wx in ((w.values, W), (S, W2)):
+        got = sdfi.certify(dev(np.c_[w.points, Sx]), dev(Wx))
+        want = oracle_cert_rows(w.points, Sx, Wx)
+        print("certify", got, want, flush=True)
+        assert (got["pair"], got["witness"]) == want
