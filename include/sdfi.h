@@ -130,6 +130,19 @@ const char *sdfi_last_error(void);
 /* Library version string. */
 const char *sdfi_version(void);
 
+/* Kernel timing for measurements.  While enabled, entry points record HIP
+ * events on the caller's stream around their main kernels, under these names:
+ * "sweep" and "resolve" (sdfi_bounds), "certify", "greedy", "witness",
+ * "rmin".  Enabling does not change results. */
+void sdfi_timing_enable(int on);
+
+/* Total milliseconds and number of launches recorded under `name` since the
+ * last reset (waits for the recorded events).  Unknown names give 0. */
+sdfi_status sdfi_timing_query(const char *name, double *ms, int64_t *launches);
+
+/* Forget all recorded timings. */
+void sdfi_timing_reset(void);
+
 /* Workspace bytes that entry point `op` needs for n samples and m queries
  * (for SDFI_OP_CERTIFY n is the set size and m is ignored). */
 sdfi_status sdfi_workspace_size(sdfi_op op, int64_t n, int64_t m, const sdfi_options *opt, size_t *bytes);

@@ -150,7 +150,27 @@ def greedy_step(q, P, S, W, tol=TOL):
     r, x, k, i = min_valid_radius(q, sigma, P, S, tol, W)
     if not math.isfinite(r):
         return math.nan, KIND_UNRESOLVED, -1, q.copy(), {}
-    return sigma * r, RMIN_KIND[k], int(i), x, {}
+    # Corollary 1: the minimal sphere covers no contour point.  A cached witness
+    # is only uncovered w.r.t. the tolerance-shrunk balls and may sit just
+    # inside the union, so witnesses inside the new ball are searched again.
+    return sigma * r, RMIN_KIND[k], int(i), x, refresh_witnesses(q, sigma * r, P, S, W, tol)
+
+
+def refresh_witnesses(q, s, P, S, W, tol=TOL):
+    """New uncovered points for the spheres whose witness lies in the new ball."""
+    updates = {}
+    rn = abs(s) - tol
+    if rn <= 0.0:
+        return updates
+    threatened = np.nonzero(dist(W, q) < rn)[0]
+    if len(threatened):
+        Pn = np.vstack([P, q[None, :]])
+        Sn = np.append(S, s)
+        for c in threatened:
+            x = uncovered_point(P[c], abs(S[c]), Pn, Sn, tol, hint=W[c])
+            if x is not None:
+                updates[int(c)] = x
+    return updates
 
 
 class GreedyResult:

@@ -2,6 +2,10 @@
 #include "common.h"
 
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
 
 namespace sdfi {
 
@@ -12,6 +16,49 @@ void set_error(const char *fmt, ...) {
     va_start(ap, fmt);
     vsnprintf(g_err, sizeof(g_err), fmt, ap);
     va_end(ap);
+}
+
+namespace {
+struct Pending {
+    std::string name;
+    hipEvent_t a, b;
+};
+std::mutex g_tm;
+bool g_timing = false;
+std::vector<Pending> g_pending;
+std::map<std::string, std::pair<double, int64_t>> g_acc;
+
+void drain_locked() {
+    for (auto &p : g_pending) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            auto &e = g_acc[p.name];
+            e.first += ms;
+            e.second += 1;
+        }
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    g_pending.clear();
+}
+}  // namespace
+
+KernelTimer::KernelTimer(const char *n, hipStream_t s) : name(n), st(s) {
+    std::lock_guard<std::mutex> lk(g_tm);
+    if (!g_timing) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        a = b = nullptr;
+        return;
+    }
+    (void)hipEventRecord(a, st);
+}
+
+void KernelTimer::stop() {
+    if (!a) return;
+    (void)hipEventRecord(b, st);
+    std::lock_guard<std::mutex> lk(g_tm);
+    g_pending.push_back({name, a, b});
+    a = b = nullptr;
 }
 
 sdfi_status read_options(const sdfi_options *opt, sdfi_options *out) {
@@ -68,6 +115,27 @@ void sdfi_default_options(sdfi_options *o) {
 }
 
 const char *sdfi_last_error(void) { return sdfi::g_err; }
+
+void sdfi_timing_enable(int on) {
+    std::lock_guard<std::mutex> lk(sdfi::g_tm);
+    sdfi::g_timing = on != 0;
+}
+
+sdfi_status sdfi_timing_query(const char *name, double *ms, int64_t *launches) {
+    SDFI_CHECK_ARG(name && ms && launches, "null argument");
+    std::lock_guard<std::mutex> lk(sdfi::g_tm);
+    sdfi::drain_locked();
+    auto it = sdfi::g_acc.find(name);
+    *ms = it == sdfi::g_acc.end() ? 0.0 : it->second.first;
+    *launches = it == sdfi::g_acc.end() ? 0 : it->second.second;
+    return SDFI_OK;
+}
+
+void sdfi_timing_reset(void) {
+    std::lock_guard<std::mutex> lk(sdfi::g_tm);
+    sdfi::drain_locked();
+    sdfi::g_acc.clear();
+}
 
 const char *sdfi_version(void) { return "sdfi 0.1 gfx950"; }
 

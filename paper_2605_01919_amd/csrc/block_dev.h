@@ -1,0 +1,250 @@
+// Work-group helpers (reductions, ordered compaction) and the work-group
+// minimum valid radius used by the greedy fallback and by the repair.
+#pragma once
+
+#include "geom_dev.h"
+
+namespace sdfi {
+namespace blk {
+
+using geom::Balls;
+using geom::Cap;
+
+template <int NW>
+struct Shared {
+    double rd[NW];
+    int64_t ri[NW];
+    int cnt[NW];
+    int counter;
+    // minimum valid radius result slots, one per wave
+    double wd[NW];
+    double wlb[NW];
+    int64_t wi[NW];
+    int wk[NW];
+    int wnd[NW];
+    double wx[NW][3];
+    unsigned long long bound_bits;
+};
+
+__device__ inline int wid() { return threadIdx.x >> 6; }
+__device__ inline int lane() { return threadIdx.x & 63; }
+
+template <int NW>
+__device__ inline double bmax(double v, Shared<NW> &S) {
+    v = geom::wmax(v);
+    if (lane() == 0) S.rd[wid()] = v;
+    __syncthreads();
+    double r = S.rd[0];
+    for (int w = 1; w < NW; ++w) r = fmax(r, S.rd[w]);
+    __syncthreads();
+    return r;
+}
+
+template <int NW>
+__device__ inline double bmin(double v, Shared<NW> &S) {
+    v = geom::wmin(v);
+    if (lane() == 0) S.rd[wid()] = v;
+    __syncthreads();
+    double r = S.rd[0];
+    for (int w = 1; w < NW; ++w) r = fmin(r, S.rd[w]);
+    __syncthreads();
+    return r;
+}
+
+template <int NW>
+__device__ inline int64_t bmin_i64(int64_t v, Shared<NW> &S) {
+    v = geom::wmin_i64(v);
+    if (lane() == 0) S.ri[wid()] = v;
+    __syncthreads();
+    int64_t r = S.ri[0];
+    for (int w = 1; w < NW; ++w) r = S.ri[w] < r ? S.ri[w] : r;
+    __syncthreads();
+    return r;
+}
+
+template <int NW>
+__device__ inline int bor(int v, Shared<NW> &S) {
+    v = geom::wor(v);
+    if (lane() == 0) S.cnt[wid()] = v;
+    __syncthreads();
+    int r = 0;
+    for (int w = 0; w < NW; ++w) r |= S.cnt[w];
+    __syncthreads();
+    return r;
+}
+
+// Append flagged items of one chunk (item base + threadIdx.x) to out[], in
+// index order; returns the new length.  All threads call it.
+template <int NW>
+__device__ inline int64_t bappend(bool flag, int64_t item, int64_t len, int64_t *out, int64_t cap, Shared<NW> &S) {
+    unsigned long long m = __ballot(flag);
+    int before = __popcll(m & ((1ull << lane()) - 1ull));
+    if (lane() == 0) S.cnt[wid()] = __popcll(m);
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int w = 0; w < NW; ++w) {
+        if (w < wid()) off += S.cnt[w];
+        tot += S.cnt[w];
+    }
+    if (flag && len + off + before < cap) out[len + off + before] = item;
+    __syncthreads();
+    return len + tot;
+}
+
+__device__ inline int sign_class(double s, double tie) { return s > tie ? 1 : (s < -tie ? -1 : 0); }
+
+// lexicographic (distance, not-deepest, lower bound, index) comparison
+__device__ inline bool better(double d, int nd, double lb, int64_t i, double d2, int nd2, double lb2, int64_t i2) {
+    if (d != d2) return d < d2;
+    if (nd != nd2) return nd < nd2;
+    if (lb != lb2) return lb < lb2;
+    return i < i2;
+}
+
+// Minimum valid radius of q for sign sigma against balls rows [0, N) of p4
+// (x, y, z, s) with known uncovered points W (rows may be NaN).  The contour
+// is that of the balls themselves (no tolerance in the geometry), so the
+// contact point clears every tolerance-shrunk ball; q counts as inside a ball
+// when d < |s| - tol.  Returns kind 0 (q in no sigma ball: radius 0),
+// 1 T, 2 D, 3 U, -1 nothing found.  list: scratch of 2 (N + 1) entries;
+// kp/kid: per wave LDS scratch.
+template <int NW>
+__device__ inline int rmin_block(const double *q, int sigma, const double *p4, const double *W, int64_t N, double tol,
+                                 double tie, int64_t *list, Cap (*kp)[geom::KMAX], int64_t (*kid)[geom::KMAX],
+                                 Shared<NW> &S, double *r_out, double *x_out, int64_t *sphere_out) {
+    const int tid = threadIdx.x;
+    const int BS = NW * 64;
+    // inside test, deepest sigma ball, and the nearest known contour point
+    double depth = -INFINITY, wbest = INFINITY;
+    int inside = 0;
+    for (int64_t c = tid; c < N; c += BS) {
+        const double *p = p4 + 4 * c;
+        if (sign_class(p[3], tie) != sigma) continue;
+        double d = geom::dist3(q, p);
+        double R = fabs(p[3]);
+        if (d < R - tol) inside = 1;
+        depth = fmax(depth, R - d);
+        if (W && !isnan(W[3 * c])) wbest = fmin(wbest, geom::dist3(W + 3 * c, q));
+    }
+    inside = bor(inside, S);
+    if (!inside) {
+        *r_out = 0.0;
+        x_out[0] = q[0];
+        x_out[1] = q[1];
+        x_out[2] = q[2];
+        *sphere_out = -1;
+        return 0;
+    }
+    depth = bmax(depth, S);
+    wbest = bmin(wbest, S);
+    int64_t deepest = INT64_MAX;
+    for (int64_t c = tid; c < N; c += BS) {
+        const double *p = p4 + 4 * c;
+        if (sign_class(p[3], tie) != sigma) continue;
+        if (fabs(p[3]) - geom::dist3(q, p) == depth) deepest = deepest < c ? deepest : c;
+    }
+    deepest = bmin_i64(deepest, S);
+    double bound = isinf(wbest) ? INFINITY : wbest * (1.0 + 1e-12) + 1e-15;
+    int64_t *lset = list + (N + 1);
+    for (int pass = 0; pass < 2; ++pass) {
+        // candidate spheres: sigma spheres passing within `bound` of q (deepest first)
+        int64_t len = 0, nl = 0;
+        for (int64_t base = 0; base < N; base += BS) {
+            int64_t c = base + tid;
+            bool f = false, inl = false;
+            if (c < N) {
+                const double *p = p4 + 4 * c;
+                double d = geom::dist3(q, p);
+                if (c != deepest && sign_class(p[3], tie) == sigma) f = fabs(d - fabs(p[3])) <= bound;
+                // the local set: balls that can cover a point within `bound` of q
+                inl = isinf(bound) || d < fabs(p[3]) + bound;
+            }
+            len = bappend(f, c, len, list + 1, N, S);
+            nl = bappend(inl, c, nl, lset, N, S);
+        }
+        if (tid == 0) list[0] = deepest;
+        ++len;
+        Balls L;
+        L.p4 = p4;
+        L.N = nl;
+        L.idx = lset;
+        L.has_extra = 0;
+        L.tol = 0.0;
+        L.skip = -1;
+        L.lq[0] = q[0];
+        L.lq[1] = q[1];
+        L.lq[2] = q[2];
+        L.lb = INFINITY;  // already applied by the index list
+        if (tid == 0) {
+            S.counter = 0;
+            S.bound_bits = __double_as_longlong(bound);
+        }
+        __syncthreads();
+        // each wave pulls spheres and keeps its own best
+        double wd = INFINITY, wlb = INFINITY, wx[3] = {0.0, 0.0, 0.0};
+        int64_t wi = INT64_MAX;
+        int wk = 0, wnd = 1;
+        const int w = wid();
+        for (int guard = 0; guard < (1 << 30); ++guard) {
+            int k = 0;
+            if (lane() == 0) k = atomicAdd(&S.counter, 1);
+            k = __shfl(k, 0, 64);
+            if (k >= len) break;
+            int64_t i = list[k];
+            const double *p = p4 + 4 * i;
+            double lbi = fabs(geom::dist3(q, p) - fabs(p[3]));
+            unsigned long long cb = 0;
+            if (lane() == 0) cb = __hip_atomic_load(&S.bound_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            double cur = __longlong_as_double((long long)__shfl(cb, 0, 64));  // wave-uniform
+            if (lbi > cur) continue;
+            double d, x[3];
+            int kk = geom::lazy_nearest(L, p, fabs(p[3]), q, cur, kp[w], kid[w], &d, x);
+            if (kk && better(d, i != deepest, lbi, i, wd, wnd, wlb, wi)) {
+                wd = d;
+                wnd = i != deepest;
+                wlb = lbi;
+                wi = i;
+                wk = kk;
+                wx[0] = x[0];
+                wx[1] = x[1];
+                wx[2] = x[2];
+                if (lane() == 0)
+                    atomicMin(&S.bound_bits, (unsigned long long)__double_as_longlong(d));
+            }
+        }
+        if (lane() == 0) {
+            S.wd[w] = wd;
+            S.wnd[w] = wnd;
+            S.wlb[w] = wlb;
+            S.wi[w] = wi;
+            S.wk[w] = wk;
+            S.wx[w][0] = wx[0];
+            S.wx[w][1] = wx[1];
+            S.wx[w][2] = wx[2];
+        }
+        __syncthreads();
+        int bw = -1;
+        for (int v = 0; v < NW; ++v) {
+            if (!S.wk[v]) continue;
+            if (bw < 0 || better(S.wd[v], S.wnd[v], S.wlb[v], S.wi[v], S.wd[bw], S.wnd[bw], S.wlb[bw], S.wi[bw]))
+                bw = v;
+        }
+        int res = -1;
+        if (bw >= 0) {
+            *r_out = S.wd[bw];
+            x_out[0] = S.wx[bw][0];
+            x_out[1] = S.wx[bw][1];
+            x_out[2] = S.wx[bw][2];
+            *sphere_out = S.wi[bw];
+            res = S.wk[bw];
+        }
+        __syncthreads();
+        if (res > 0) return res;
+        if (isinf(bound)) break;
+        bound = INFINITY;  // the witness bound was not beaten: search without it
+    }
+    return -1;
+}
+
+}  // namespace blk
+}  // namespace sdfi

@@ -325,11 +325,15 @@ sdfi_status launch(const double *samples, int64_t n, const double *queries, int6
     }
     SDFI_HIP(hipMemsetAsync(b.overflows, 0, sizeof(int64_t), st));
     const int64_t per = (int64_t)BT * QPT;
+    KernelTimer t1("sweep", st);
     sweep_kernel<T, QPT><<<(unsigned)((m + per - 1) / per), BT, 0, st>>>(pts, (int)n, queries, m, eps, b.o);
+    t1.stop();
     SDFI_HIP(hipGetLastError());
+    KernelTimer t2("resolve", st);
     resolve_kernel<T><<<(unsigned)((m + 3) / 4), 256, 0, st>>>(samples, n, queries, m, eps, b.o, opt.tol,
                                                                 opt.tie_tol, lo, hi, argmax, argmin, flags,
                                                                 b.overflows);
+    t2.stop();
     SDFI_HIP(hipGetLastError());
     if (overflow_count) {
         SDFI_HIP(hipMemcpyAsync(overflow_count, b.overflows, sizeof(int64_t), hipMemcpyDeviceToHost, st));

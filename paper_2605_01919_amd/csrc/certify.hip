@@ -127,7 +127,9 @@ sdfi_status run_certify(const double *pv, const double *wit, int64_t N, int64_t 
         const int64_t per = (int64_t)BT * RPT;
         // float32 margin error: < 2e-6 for magnitudes <= 2 (two distances and a
         // difference of rounded values); screen with 4e-6
+        KernelTimer tm("certify", st);
         certify_kernel<<<(unsigned)((N + per - 1) / per), BT, 0, st>>>(pf, pv, wit, N, o.tol, 4e-6f, cnt);
+        tm.stop();
         SDFI_HIP(hipGetLastError());
     }
     Cnt h;

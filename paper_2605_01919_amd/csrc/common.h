@@ -32,6 +32,15 @@ void set_error(const char *fmt, ...);
         }                                                                       \
     } while (0)
 
+// Records a pair of HIP events around a kernel when timing is enabled.
+struct KernelTimer {
+    hipEvent_t a = nullptr, b = nullptr;
+    const char *name;
+    hipStream_t st;
+    KernelTimer(const char *name, hipStream_t st);
+    void stop();
+};
+
 // Validated copy of the caller's options (defaults when opt == NULL).
 sdfi_status read_options(const sdfi_options *opt, sdfi_options *out);
 

@@ -1,0 +1,606 @@
+// Device geometry of the exact validity tests (Prop. 1 (ii)) and of the
+// minimum valid radius (proof of Prop. 2), in float64, one wavefront each.
+//
+// A ball (p, s) covers point x of sphere (o, r) when |x - p| < |s| - tol.
+// In unit directions v = (x - o)/r that is the open cap v.u > c with
+//   u = (p - o)/D, c = (r^2 + D^2 - R^2)/(2 r D), D = |p - o|, R = |s| - tol.
+// The rim of cap e is v(t) = c_e u_e + rho_e (cos t e1 + sin t e2); cap f
+// covers the open arc A cos t + B sin t > K of that rim with
+//   A = rho_e e1.u_f, B = rho_e e2.u_f, K = c_f - c_e u_e.u_f.
+//
+// Rim walk.  Starting at an angle, if some arcs cover it, jump to the
+// farthest end among them; stop at the first angle no arc covers or after a
+// full turn (rim covered).  Each arc is jumped over at most once per turn.
+//
+// Lazy search.  A sphere with caps K has an uncovered point iff it has one
+// w.r.t. every subset; the search keeps a working subset K' (<= KMAX caps in
+// LDS), finds uncovered points w.r.t. K' by rim walks, and verifies them
+// against all caps.  A verified point is a true witness; a candidate covered
+// by cap f adds f to K'.  If K' covers the sphere, so does K.  The nearest
+// uncovered point to q is found the same way: the K'-nearest point is never
+// farther than the true one, so a verified K'-nearest point is the answer.
+// When K' is full the search falls back to walking every rim of K.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+namespace sdfi {
+namespace geom {
+
+constexpr int KMAX = 64;             // working cap subset per wavefront
+constexpr double TWO_PI = 6.283185307179586476925286766559;
+constexpr double ARC_EPS = 1e-12;    // angles within this of an arc end count as uncovered
+constexpr double NUDGE = 1e-7;       // witnesses move this far (rad) off the rim they sit on
+constexpr double COVER_EPS = 1e-13;  // cover margins v.u - c up to this count as uncovered (rounding)
+
+enum { ST_NONE = 0, ST_FOUND = 1, ST_NUMERIC = 2 };
+
+struct Cap {
+    double u[3];
+    double c;
+};
+
+// The balls of a search: rows [0, N) of p4 (x, y, z, s), plus an optional
+// extra ball, minus ball `skip`.  Balls are shrunk by `tol`.  With `lb < inf`
+// only balls with |lq - p| < |s| + lb take part (a local set: balls that can
+// cover a point within lb of lq).
+struct Balls {
+    const double *p4;
+    int64_t N;
+    double extra[4];
+    int has_extra;
+    double tol;
+    int64_t skip;
+    double lq[3];
+    double lb;
+    const int64_t *idx;  // optional: the balls are rows idx[0..N) of p4 instead of [0, N)
+};
+
+__device__ inline double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+__device__ inline double dist3(const double *a, const double *b) {
+#pragma clang fp contract(off)
+    double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+    return sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+__device__ inline const double *ball_ptr(const Balls &B, int64_t f) {
+    if (f >= B.N) return B.extra;
+    return B.p4 + 4 * (B.idx ? B.idx[f] : f);
+}
+__device__ inline int64_t ball_count(const Balls &B) { return B.N + (B.has_extra ? 1 : 0); }
+
+// cap of ball f on sphere (o, r): 0 = no cap, 1 = cap written, 2 = the ball holds the whole sphere
+__device__ inline int cap_of(const Balls &B, int64_t f, const double *o, double r, Cap &cap) {
+#pragma clang fp contract(off)
+    if (f == B.skip) return 0;
+    const double *p = ball_ptr(B, f);
+    if (B.lb < INFINITY && !(dist3(B.lq, p) < fabs(p[3]) + B.lb)) return 0;
+    double R = fabs(p[3]) - B.tol;
+    if (!(R > 0.0)) return 0;
+    double v[3] = {p[0] - o[0], p[1] - o[1], p[2] - o[2]};
+    double D = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    if (D + r < R) return 2;
+    if (!(D > 0.0) || !(fabs(D - r) < R)) return 0;
+    cap.u[0] = v[0] / D;
+    cap.u[1] = v[1] / D;
+    cap.u[2] = v[2] / D;
+    cap.c = (r * r + D * D - R * R) / (2.0 * r * D);
+    return 1;
+}
+
+__device__ inline void basis(const double *u, double *e1, double *e2) {
+    // e1 = u x a (a the x axis unless u is close to it), e2 = u x e1
+    double a[3] = {1.0, 0.0, 0.0};
+    if (fabs(u[0]) >= 0.9) {
+        a[0] = 0.0;
+        a[1] = 1.0;
+    }
+    e1[0] = u[1] * a[2] - u[2] * a[1];
+    e1[1] = u[2] * a[0] - u[0] * a[2];
+    e1[2] = u[0] * a[1] - u[1] * a[0];
+    double n = sqrt(dot3(e1, e1));
+    e1[0] /= n;
+    e1[1] /= n;
+    e1[2] /= n;
+    e2[0] = u[1] * e1[2] - u[2] * e1[1];
+    e2[1] = u[2] * e1[0] - u[0] * e1[2];
+    e2[2] = u[0] * e1[1] - u[1] * e1[0];
+}
+
+struct Rim {
+    double u[3], c, rho, e1[3], e2[3];
+};
+
+__device__ inline void make_rim(const Cap &cp, Rim &R) {
+    R.u[0] = cp.u[0];
+    R.u[1] = cp.u[1];
+    R.u[2] = cp.u[2];
+    R.c = cp.c;
+    R.rho = sqrt(fmax(0.0, 1.0 - cp.c * cp.c));
+    basis(cp.u, R.e1, R.e2);
+}
+
+__device__ inline void rim_dir(const Rim &R, double t, double *v) {
+    double ct = cos(t), st = sin(t);
+    for (int j = 0; j < 3; ++j) v[j] = R.c * R.u[j] + R.rho * (ct * R.e1[j] + st * R.e2[j]);
+}
+
+// arc of cap f on rim R: returns 0 none, 1 arc (phi, beta), 2 whole rim
+__device__ inline int arc_of(const Rim &R, const Cap &f, double &A, double &Bc, double &K, double &amp) {
+    A = R.rho * dot3(R.e1, f.u);
+    Bc = R.rho * dot3(R.e2, f.u);
+    K = f.c - R.c * dot3(R.u, f.u);
+    amp = hypot(A, Bc);
+    if (K < -amp) return 2;
+    if (!(amp > K)) return 0;
+    return 1;
+}
+
+__device__ inline double wrap_pos(double d) {
+    // into (0, 2 pi]
+    d = fmod(d, TWO_PI);
+    if (d <= 0.0) d += TWO_PI;
+    return d;
+}
+
+// Walk rim R over caps kp[0..k) (skipping index `self`) from angle t0 in
+// direction dir (+1 forward to arc ends, -1 backward to arc starts).
+// Returns 1 with *t_out = first uncovered angle and *adv its distance from t0,
+// 0 if the rim is covered, 2 if the step cap was hit.
+__device__ inline int rim_walk(const Rim &R, const Cap *kp, int k, int self, double t0, int dir, double *t_out,
+                               double *adv_out) {
+    double t = t0, adv = 0.0;
+    for (int it = 0; it <= k + 4; ++it) {
+        double ct = cos(t), st = sin(t);
+        double step = 0.0;
+        bool cov = false;
+        for (int f = 0; f < k; ++f) {
+            if (f == self) continue;
+            double A, Bc, K, amp;
+            int a = arc_of(R, kp[f], A, Bc, K, amp);
+            if (a == 2) return 0;
+            if (a == 0) continue;
+            double val = A * ct + Bc * st - K;
+            if (!(val > ARC_EPS * amp)) continue;
+            cov = true;
+            double phi = atan2(Bc, A);
+            double beta = acos(fmin(1.0, fmax(-1.0, K / amp)));
+            double d = dir > 0 ? wrap_pos(phi + beta - t) : wrap_pos(t - (phi - beta));
+            step = fmax(step, d);
+        }
+        if (!cov) {
+            *t_out = t;
+            *adv_out = adv;
+            return 1;
+        }
+        adv += step;
+        if (adv >= TWO_PI) return 0;
+        t += dir > 0 ? step : -step;
+    }
+    return 2;
+}
+
+// angular length of the uncovered gap that starts at t (forward), <= 2 pi
+__device__ inline double gap_length(const Rim &R, const Cap *kp, int k, int self, double t) {
+    double best = TWO_PI;
+    for (int f = 0; f < k; ++f) {
+        if (f == self) continue;
+        double A, Bc, K, amp;
+        if (arc_of(R, kp[f], A, Bc, K, amp) != 1) continue;
+        double phi = atan2(Bc, A);
+        double beta = acos(fmin(1.0, fmax(-1.0, K / amp)));
+        best = fmin(best, wrap_pos(phi - beta - t));
+    }
+    return best;
+}
+
+// ---- wave-level helpers (all 64 lanes call them together) ----
+
+__device__ inline double wmax(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ inline double wmin(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ inline int64_t wmin_i64(int64_t v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        int64_t w = __shfl_xor(v, o, 64);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+__device__ inline void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ inline int wor(int v) {
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Largest cover margin v.u_f - c_f over all caps of the sphere (ball `excl`
+// left out) and the smallest ball index attaining it; also reports a ball
+// holding the whole sphere.  margin > 0 means v is covered.
+__device__ inline void wave_cover(const Balls &B, const double *o, double r, const double *v, int64_t excl,
+                                  double *mx, int64_t *arg, int *whole) {
+    const int lane = threadIdx.x & 63;
+    double best = -INFINITY;
+    int64_t bi = INT64_MAX;
+    int wh = 0;
+    const int64_t n = ball_count(B);
+    for (int64_t f = lane; f < n; f += 64) {
+        if (f == excl) continue;
+        Cap cp;
+        int s = cap_of(B, f, o, r, cp);
+        if (s == 2) {
+            wh = 1;
+            continue;
+        }
+        if (s == 0) continue;
+        double m = dot3(v, cp.u) - cp.c;
+        if (m > best) {
+            best = m;
+            bi = f;
+        }
+    }
+    double g = wmax(best);
+    int64_t cand = (best == g) ? bi : INT64_MAX;
+    *mx = g;
+    *arg = wmin_i64(cand);
+    *whole = wor(wh);
+}
+
+// Exact: does sphere (o, r) have a point no ball covers?  Writes one (nudged
+// off the rim it was found on) to x.  kp: this wave's LDS scratch (KMAX caps),
+// kid: their ball indices.  hint orders the search only.
+__device__ inline int lazy_exist(const Balls &B, const double *o, double r, const double *hint, Cap *kp,
+                                 int64_t *kid, double *x) {
+    const int lane = threadIdx.x & 63;
+    if (!(r > 0.0)) {
+        // a sphere of radius 0 is its centre: covered iff |o - p| < |s| - tol for some ball
+        double best = -INFINITY;
+        const int64_t n = ball_count(B);
+        for (int64_t f = lane; f < n; f += 64) {
+            if (f == B.skip) continue;
+            const double *p = ball_ptr(B, f);
+            if (B.lb < INFINITY && !(dist3(B.lq, p) < fabs(p[3]) + B.lb)) continue;
+            best = fmax(best, fabs(p[3]) - B.tol - dist3(o, p));
+        }
+        if (wmax(best) > 0.0) return ST_NONE;
+        x[0] = o[0];
+        x[1] = o[1];
+        x[2] = o[2];
+        return ST_FOUND;
+    }
+    double vh[3] = {1.0, 0.0, 0.0};
+    if (hint) {
+        double g[3] = {hint[0] - o[0], hint[1] - o[1], hint[2] - o[2]};
+        double gn = sqrt(dot3(g, g));
+        if (gn > 0.0) {
+            vh[0] = g[0] / gn;
+            vh[1] = g[1] / gn;
+            vh[2] = g[2] / gn;
+        }
+    }
+    double mx;
+    int64_t arg;
+    int whole;
+    wave_cover(B, o, r, vh, -1, &mx, &arg, &whole);
+    if (whole) return ST_NONE;
+    if (!(mx > COVER_EPS)) {
+        for (int j = 0; j < 3; ++j) x[j] = o[j] + r * vh[j];
+        return ST_FOUND;
+    }
+    int k = 0;
+    if (lane == 0) {
+        kid[0] = arg;
+        cap_of(B, arg, o, r, kp[0]);
+    }
+    k = 1;
+    wave_sync_lds();
+    for (int round = 0; round < 4 * KMAX; ++round) {
+        // 1. uncovered gap midpoints w.r.t. the working subset, one rim per lane
+        int found = 0, numeric = 0;
+        double tmid = 0.0;
+        Rim R;
+        if (lane < k) {
+            make_rim(kp[lane], R);
+            double t, adv;
+            int st = rim_walk(R, kp, k, lane, 0.0, 1, &t, &adv);
+            if (st == 1) {
+                found = 1;
+                tmid = t + 0.5 * gap_length(R, kp, k, lane, t);
+            } else if (st == 2) {
+                numeric = 1;
+            }
+        }
+        if (!wor(found)) {
+            if (wor(numeric)) break;  // no proof of coverage: fall back
+            return ST_NONE;           // the subset covers the sphere
+        }
+        // 2. verify candidates in lane order; collect the cap covering each
+        int added = 0;
+        for (int cl = 0; cl < k; ++cl) {
+            int f_cl = __shfl(found, cl, 64);
+            if (!f_cl) continue;
+            double v[3] = {0.0, 0.0, 0.0};
+            if (lane == cl) rim_dir(R, tmid, v);
+            v[0] = __shfl(v[0], cl, 64);
+            v[1] = __shfl(v[1], cl, 64);
+            v[2] = __shfl(v[2], cl, 64);
+            int64_t self = kid[cl];
+            wave_cover(B, o, r, v, self, &mx, &arg, &whole);
+            if (!(mx > COVER_EPS)) {
+                // verified; try to move it off the rim of `self`
+                double uv = dot3(kp[cl].u, v);
+                double tg[3] = {kp[cl].u[0] - uv * v[0], kp[cl].u[1] - uv * v[1], kp[cl].u[2] - uv * v[2]};
+                double tn = sqrt(dot3(tg, tg));
+                if (tn > 0.0) {
+                    double w[3] = {v[0] - NUDGE * tg[0] / tn, v[1] - NUDGE * tg[1] / tn, v[2] - NUDGE * tg[2] / tn};
+                    double wn = sqrt(dot3(w, w));
+                    w[0] /= wn;
+                    w[1] /= wn;
+                    w[2] /= wn;
+                    double m2;
+                    int64_t a2;
+                    int wh2;
+                    wave_cover(B, o, r, w, -1, &m2, &a2, &wh2);
+                    if (!(m2 > COVER_EPS)) {
+                        v[0] = w[0];
+                        v[1] = w[1];
+                        v[2] = w[2];
+                    }
+                }
+                for (int j = 0; j < 3; ++j) x[j] = o[j] + r * v[j];
+                return ST_FOUND;
+            }
+            // add the covering cap unless already present
+            bool have = false;
+            for (int e = 0; e < k; ++e) have |= (kid[e] == arg);
+            if (!have && k < KMAX) {
+                if (lane == 0) {
+                    kid[k] = arg;
+                    cap_of(B, arg, o, r, kp[k]);
+                }
+                wave_sync_lds();
+                ++k;
+                ++added;
+            }
+        }
+        wave_sync_lds();
+        if (added == 0) break;  // subset full or no progress: fall back
+    }
+    // Fallback: walk every rim of every cap (lanes over rims), caps recomputed.
+    const int64_t n = ball_count(B);
+    int64_t first = INT64_MAX;
+    double fx[3] = {0.0, 0.0, 0.0};
+    for (int64_t e0 = 0; e0 < n; e0 += 64) {
+        int64_t e = e0 + lane;
+        if (e < n) {
+            Cap ce;
+            if (cap_of(B, e, o, r, ce) == 1) {
+                Rim R;
+                make_rim(ce, R);
+                // walk over all caps f != e, streamed in chunks of KMAX through registers
+                double t = 0.0, adv = 0.0;
+                int ok = 0;
+                for (int64_t it = 0; it < n + 8; ++it) {
+                    double ct = cos(t), st = sin(t), step = 0.0;
+                    bool cov = false, whole_rim = false;
+                    for (int64_t f = 0; f < n; ++f) {
+                        if (f == e) continue;
+                        Cap cf;
+                        int s = cap_of(B, f, o, r, cf);
+                        if (s != 1) continue;
+                        double A, Bc, K, amp;
+                        int a = arc_of(R, cf, A, Bc, K, amp);
+                        if (a == 2) {
+                            whole_rim = true;
+                            break;
+                        }
+                        if (a == 0) continue;
+                        if (!(A * ct + Bc * st - K > ARC_EPS * amp)) continue;
+                        cov = true;
+                        double phi = atan2(Bc, A), beta = acos(fmin(1.0, fmax(-1.0, K / amp)));
+                        step = fmax(step, wrap_pos(phi + beta - t));
+                    }
+                    if (whole_rim) break;
+                    if (!cov) {
+                        ok = 1;
+                        break;
+                    }
+                    adv += step;
+                    if (adv >= TWO_PI) break;
+                    t += step;
+                }
+                if (ok && e < first) {
+                    first = e;
+                    double v[3];
+                    rim_dir(R, t, v);
+                    for (int j = 0; j < 3; ++j) fx[j] = o[j] + r * v[j];
+                }
+            }
+        }
+        int64_t g = wmin_i64(first);
+        if (g != INT64_MAX) {
+            int src = (int)(g - e0);
+            for (int j = 0; j < 3; ++j) x[j] = __shfl(fx[j], src, 64);
+            return ST_FOUND;
+        }
+    }
+    return ST_NONE;
+}
+
+// Nearest point to q of the uncovered part of sphere (o, r) if nearer than
+// bound (strictly less or equal kept: ties are broken by the caller).
+// Returns 0 none, 1 radial foot point (T), 2 rim nearest point (D), 3 rim arc
+// end (U); writes distance and point.
+__device__ inline int lazy_nearest(const Balls &B, const double *o, double r, const double *q, double bound, Cap *kp,
+                                   int64_t *kid, double *dist_out, double *x) {
+    const int lane = threadIdx.x & 63;
+    double g[3] = {q[0] - o[0], q[1] - o[1], q[2] - o[2]};
+    double gn = sqrt(dot3(g, g));
+    double mx;
+    int64_t arg;
+    int whole;
+    if (!(gn > 0.0)) {
+        if (r > bound) return 0;
+        int s = lazy_exist(B, o, r, nullptr, kp, kid, x);
+        if (s != ST_FOUND) return 0;
+        *dist_out = r;
+        return 1;
+    }
+    double v0[3] = {g[0] / gn, g[1] / gn, g[2] / gn};
+    double d0 = fabs(gn - r);
+    if (d0 > bound) return 0;
+    wave_cover(B, o, r, v0, -1, &mx, &arg, &whole);
+    if (whole) return 0;
+    if (!(mx > COVER_EPS)) {
+        for (int j = 0; j < 3; ++j) x[j] = o[j] + r * v0[j];
+        *dist_out = d0;
+        return 1;
+    }
+    int k = 1;
+    if (lane == 0) {
+        kid[0] = arg;
+        cap_of(B, arg, o, r, kp[0]);
+    }
+    wave_sync_lds();
+    for (int round = 0; round < 8 * KMAX; ++round) {
+        double cd = INFINITY, ct_ = 0.0;
+        int ckind = 0;
+        Rim R;
+        if (lane < k) {
+            make_rim(kp[lane], R);
+            // lower bound: distance from q to the rim circle
+            double ug = dot3(R.u, g);
+            double perp = sqrt(fmax(gn * gn - ug * ug, 0.0));
+            double vg = R.c * ug + R.rho * perp;
+            double lbd = sqrt(fmax(r * r + gn * gn - 2.0 * r * vg, 0.0));
+            if (lbd <= bound) {
+                double ts = atan2(dot3(R.e2, g), dot3(R.e1, g));
+                double tp, ap, tm, am;
+                int sp = rim_walk(R, kp, k, lane, ts, 1, &tp, &ap);
+                if (sp == 1 && ap == 0.0) {
+                    ct_ = ts;
+                    ckind = 2;
+                } else if (sp == 1) {
+                    int sm = rim_walk(R, kp, k, lane, ts, -1, &tm, &am);
+                    ct_ = (sm == 1 && am < ap) ? tm : tp;
+                    ckind = 3;
+                }
+                if (ckind) {
+                    double v[3];
+                    rim_dir(R, ct_, v);
+                    double y[3] = {o[0] + r * v[0], o[1] + r * v[1], o[2] + r * v[2]};
+                    cd = dist3(y, q);
+                    if (cd > bound) {
+                        ckind = 0;
+                        cd = INFINITY;
+                    }
+                }
+            }
+        }
+        double best = wmin(cd);
+        if (best == INFINITY) return 0;
+        // lowest lane with the best distance
+        int64_t cand = (cd == best && ckind) ? lane : INT64_MAX;
+        int src = (int)wmin_i64(cand);
+        double v[3] = {0.0, 0.0, 0.0};
+        if (lane == src) rim_dir(R, ct_, v);
+        v[0] = __shfl(v[0], src, 64);
+        v[1] = __shfl(v[1], src, 64);
+        v[2] = __shfl(v[2], src, 64);
+        int kind = __shfl(ckind, src, 64);
+        wave_cover(B, o, r, v, kid[src], &mx, &arg, &whole);
+        if (!(mx > COVER_EPS)) {
+            for (int j = 0; j < 3; ++j) x[j] = o[j] + r * v[j];
+            *dist_out = best;
+            return kind;
+        }
+        bool have = false;
+        for (int e = 0; e < k; ++e) have |= (kid[e] == arg);
+        if (have || k >= KMAX) break;
+        if (lane == 0) {
+            kid[k] = arg;
+            cap_of(B, arg, o, r, kp[k]);
+        }
+        wave_sync_lds();
+        ++k;
+    }
+    // Fallback: every rim against every cap.
+    const int64_t n = ball_count(B);
+    double bd = INFINITY, bx[3] = {0.0, 0.0, 0.0};
+    int bkind = 0;
+    for (int64_t e = lane; e < n; e += 64) {
+        Cap ce;
+        if (cap_of(B, e, o, r, ce) != 1) continue;
+        Rim R;
+        make_rim(ce, R);
+        double ts = atan2(dot3(R.e2, g), dot3(R.e1, g));
+        double tt[2];
+        int kinds[2] = {0, 0};
+        for (int dir = 0; dir < 2; ++dir) {
+            double t = ts, adv = 0.0;
+            for (int64_t it = 0; it < n + 8; ++it) {
+                double ct = cos(t), st = sin(t), step = 0.0;
+                bool cov = false, whole_rim = false;
+                for (int64_t f = 0; f < n; ++f) {
+                    if (f == e) continue;
+                    Cap cf;
+                    if (cap_of(B, f, o, r, cf) != 1) continue;
+                    double A, Bc, K, amp;
+                    int a = arc_of(R, cf, A, Bc, K, amp);
+                    if (a == 2) {
+                        whole_rim = true;
+                        break;
+                    }
+                    if (a == 0 || !(A * ct + Bc * st - K > ARC_EPS * amp)) continue;
+                    cov = true;
+                    double phi = atan2(Bc, A), beta = acos(fmin(1.0, fmax(-1.0, K / amp)));
+                    step = fmax(step, dir == 0 ? wrap_pos(phi + beta - t) : wrap_pos(t - (phi - beta)));
+                }
+                if (whole_rim) break;
+                if (!cov) {
+                    tt[dir] = t;
+                    kinds[dir] = adv == 0.0 ? 2 : 3;
+                    break;
+                }
+                adv += step;
+                if (adv >= TWO_PI) break;
+                t += dir == 0 ? step : -step;
+            }
+        }
+        for (int dir = 0; dir < 2; ++dir) {
+            if (!kinds[dir]) continue;
+            double v[3];
+            rim_dir(R, tt[dir], v);
+            double y[3] = {o[0] + r * v[0], o[1] + r * v[1], o[2] + r * v[2]};
+            double d = dist3(y, q);
+            if (d < bd) {
+                bd = d;
+                bkind = kinds[dir];
+                bx[0] = y[0];
+                bx[1] = y[1];
+                bx[2] = y[2];
+            }
+        }
+    }
+    double best = wmin(bd);
+    if (!(best <= bound)) return 0;
+    int64_t cand = (bd == best) ? lane : INT64_MAX;
+    int src = (int)wmin_i64(cand);
+    for (int j = 0; j < 3; ++j) x[j] = __shfl(bx[j], src, 64);
+    *dist_out = best;
+    return __shfl(bkind, src, 64);
+}
+
+}  // namespace geom
+}  // namespace sdfi

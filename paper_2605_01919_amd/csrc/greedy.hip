@@ -1,0 +1,681 @@
+// Greedy sequential interpolation (Sec. 3.3 interpolate_sdf_to applied in the
+// refinement order of Sec. 4) and the per-sample witness search.
+//
+// One work-group of 1024 threads owns one instance and assigns its queries
+// one after another, exactly as the sequential definition: for query q the
+// work-group reduces the cone bounds over every constraint accepted so far
+// (samples, then earlier queries), ranks the candidates hi and lo by the
+// paper's score sign_score * |s|, and accepts the first one that keeps the
+// set valid (Prop. 1):
+//   - the new sphere keeps an uncovered point: its tangent point if no ball
+//     covers it, else an exact search on the new sphere (one wavefront);
+//   - every existing sphere keeps an uncovered point: spheres whose cached
+//     witness falls inside the new ball are re-searched exactly with the new
+//     ball added (wavefronts in parallel).
+// Otherwise it takes 0 (outside every ball) or the minimum valid radius
+// (all 16 wavefronts).  Batched instances run as independent work-groups of
+// the same launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "block_dev.h"
+#include "common.h"
+
+namespace sdfi {
+
+namespace {
+
+constexpr int NW = 16;  // wavefronts per greedy work-group
+constexpr int GBS = NW * 64;
+
+enum {
+    C_HI = 0, C_LO, C_ZERO, C_RMIN, C_COINC, C_INFEAS, C_UNRES, C_SEARCH, C_NUMERIC, C_NCOUNT
+};
+
+struct GInst {
+    const double *samples;   // n x 4
+    const double *queries;   // m x 3
+    const int64_t *order;    // m
+    const double *w_in;      // n x 3 sample witnesses (NaN = none)
+    double *values;
+    int64_t *active;
+    uint8_t *kind;
+    double *witness;         // m x 3
+    double *sample_witness;  // n x 3 or null
+    int64_t *order_out;
+    double *CP;              // (n + m) x 4 constraints
+    double *CW;              // (n + m) x 3 witnesses
+    int64_t *CSRC;           // (n + m) query index of each appended constraint
+    int64_t *list;           // 2 (n + m + 1) scratch
+    double *pend;            // (n + m) x 3 pending witness updates
+    unsigned long long *counts;  // C_NCOUNT
+    int64_t n, m;
+};
+
+struct StepShared {
+    blk::Shared<NW> S;
+    geom::Cap kp[NW][geom::KMAX];
+    int64_t kid[NW][geom::KMAX];
+    double x[3];
+    int status;
+    int fail;
+    int counter;
+};
+
+__device__ inline bool in_domain(const double *w, const double *dlo, const double *dhi, double tol) {
+    for (int j = 0; j < 3; ++j)
+        if (!(w[j] >= dlo[j] - tol && w[j] <= dhi[j] + tol)) return false;
+    return true;
+}
+
+// indices c with |W_c - q| < rn, in index order, into I.list; returns the count
+__device__ int64_t threatened(const GInst &I, int64_t N, const double *q, double rn, int64_t n, int64_t m,
+                              StepShared &SH) {
+    int64_t cnt = 0;
+    if (rn > 0.0) {
+        for (int64_t base = 0; base < N; base += GBS) {
+            int64_t c = base + threadIdx.x;
+            bool f = c < N && geom::dist3(I.CW + 3 * c, q) < rn;
+            cnt = blk::bappend(f, c, cnt, I.list, n + m + 1, SH.S);
+        }
+    }
+    return cnt > n + m ? n + m : cnt;
+}
+
+// Exact re-search of the threatened spheres with the ball (q, s) added, waves
+// in parallel; results into I.pend.  SH.fail = 1 if some sphere has no
+// uncovered point left (with `keep_going` the search continues and such
+// spheres keep their old witness).
+__device__ void revalidate(const GInst &I, int64_t N, const double *q, double s, int64_t nthr, double tol,
+                           StepShared &SH, bool keep_going) {
+    const int w = blk::wid(), ln = blk::lane();
+    if (threadIdx.x == 0) {
+        SH.fail = 0;
+        SH.counter = 0;
+    }
+    __syncthreads();
+    if (nthr > 0) {
+        geom::Balls B;
+        B.p4 = I.CP;
+        B.N = N;
+        B.extra[0] = q[0];
+        B.extra[1] = q[1];
+        B.extra[2] = q[2];
+        B.extra[3] = s;
+        B.has_extra = 1;
+        B.tol = tol;
+        B.lb = INFINITY;
+        B.idx = nullptr;
+        for (int64_t guard = 0; guard <= nthr; ++guard) {
+            int t = 0;
+            if (ln == 0) t = atomicAdd(&SH.counter, 1);
+            t = __shfl(t, 0, 64);
+            if (t >= nthr) break;
+            int fl = 0;
+            if (ln == 0) fl = __hip_atomic_load(&SH.fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (__shfl(fl, 0, 64) && !keep_going) break;  // wave-uniform
+            int64_t c = I.list[t];
+            B.skip = c;
+            const double *p = I.CP + 4 * c;
+            double x[3];
+            int st = geom::lazy_exist(B, p, fabs(p[3]), I.CW + 3 * c, SH.kp[w], SH.kid[w], x);
+            if (ln == 0) {
+                atomicAdd(&I.counts[C_SEARCH], 1ull);
+                if (st == geom::ST_NUMERIC) atomicAdd(&I.counts[C_NUMERIC], 1ull);
+                bool ok = st == geom::ST_FOUND;
+                if (!ok) atomicOr(&SH.fail, 1);
+                for (int j = 0; j < 3; ++j) I.pend[3 * t + j] = ok ? x[j] : I.CW[3 * c + j];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(GBS) void greedy_kernel(const GInst *insts, double tol, double tie, double dlo0,
+                                                     double dlo1, double dlo2, double dhi0, double dhi1,
+                                                     double dhi2) {
+    __shared__ StepShared SH;
+    const GInst I = insts[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int w = blk::wid(), ln = blk::lane();
+    const double dlo[3] = {dlo0, dlo1, dlo2}, dhi[3] = {dhi0, dhi1, dhi2};
+    const int64_t n = I.n, m = I.m;
+    for (int64_t c = tid; c < n; c += GBS) {
+        for (int j = 0; j < 4; ++j) I.CP[4 * c + j] = I.samples[4 * c + j];
+        for (int j = 0; j < 3; ++j) I.CW[3 * c + j] = I.w_in[3 * c + j];
+        I.CSRC[c] = -1;
+    }
+    if (tid < C_NCOUNT) I.counts[tid] = 0;
+    __syncthreads();
+    __threadfence_block();
+    int64_t N = n;
+    for (int64_t k = 0; k < m; ++k) {
+        const int64_t j = I.order[k];
+        const double q[3] = {I.queries[3 * j], I.queries[3 * j + 1], I.queries[3 * j + 2]};
+        // ---- cone bounds over all constraints (Sec. 4.3) ----
+        double lo = -INFINITY, hi = INFINITY;
+        for (int64_t c = tid; c < N; c += GBS) {
+            const double *p = I.CP + 4 * c;
+            double d = geom::dist3(q, p);
+            lo = fmax(lo, p[3] - d);
+            hi = fmin(hi, p[3] + d);
+        }
+        lo = blk::bmax(lo, SH.S);
+        hi = blk::bmin(hi, SH.S);
+        int64_t a = INT64_MAX, b = INT64_MAX;
+        for (int64_t c = tid; c < N; c += GBS) {
+            const double *p = I.CP + 4 * c;
+            double d = geom::dist3(q, p);
+            if (p[3] - d >= lo - tie && c < a) a = c;
+            if (p[3] + d <= hi + tie && c < b) b = c;
+        }
+        a = blk::bmin_i64(a, SH.S);
+        b = blk::bmin_i64(b, SH.S);
+        if (a == INT64_MAX || b == INT64_MAX) lo = NAN;  // only with NaN inputs
+        double val = NAN, wq[3] = {q[0], q[1], q[2]};
+        int kindv = 0;
+        int64_t act = -1;
+        int accepted = 0;
+        int npend = 0;
+        int64_t nthr = 0;
+        if (!(lo <= hi + tol)) {
+            kindv = SDFI_KIND_INFEASIBLE;
+        } else {
+            const double *pa = I.CP + 4 * a, *pb = I.CP + 4 * b;
+            const double da = geom::dist3(q, pa), db = geom::dist3(q, pb);
+            if (da <= tie || db <= tie) {
+                int64_t c = da <= tie ? a : b;
+                val = I.CP[4 * c + 3];
+                kindv = SDFI_KIND_COINCIDENT;
+                act = c;
+                for (int jj = 0; jj < 3; ++jj) wq[jj] = I.CW[3 * c + jj];
+                accepted = 2;
+            } else {
+                // candidates: hi tangent to b at p_b - s_b u_b, lo tangent to a at p_a + s_a u_a
+                double cs[2], cw[2][3];
+                int64_t ct[2];
+                int ck[2];
+                double sh = (hi > 0.0 ? 1.0 : 2.0) * fabs(hi), sl = (lo > 0.0 ? 1.0 : 2.0) * fabs(lo);
+                bool hi_first;
+                if (fabs(sh - sl) <= tie)
+                    hi_first = !(lo < 0.0 && hi >= 0.0);
+                else
+                    hi_first = sh > sl;
+                for (int e = 0; e < 2; ++e) {
+                    bool is_hi = (e == 0) == hi_first;
+                    const double *pt = is_hi ? pb : pa;
+                    double dt = is_hi ? db : da;
+                    double s = is_hi ? hi : lo;
+                    double sgn = is_hi ? -1.0 : 1.0;
+                    for (int jj = 0; jj < 3; ++jj) cw[e][jj] = pt[jj] + sgn * pt[3] * (q[jj] - pt[jj]) / dt;
+                    cs[e] = s;
+                    ct[e] = is_hi ? b : a;
+                    ck[e] = is_hi ? SDFI_KIND_HI : SDFI_KIND_LO;
+                }
+                for (int e = 0; e < 2 && !accepted; ++e) {
+                    if (!in_domain(cw[e], dlo, dhi, tol)) continue;
+                    const double s = cs[e], r = fabs(s);
+                    // new sphere: tangent point uncovered?
+                    int cov = 0;
+                    for (int64_t c = tid; c < N; c += GBS) {
+                        const double *p = I.CP + 4 * c;
+                        if (geom::dist3(cw[e], p) < fabs(p[3]) - tol) cov = 1;
+                    }
+                    cov = blk::bor(cov, SH.S);
+                    double nw[3] = {cw[e][0], cw[e][1], cw[e][2]};
+                    if (cov) {
+                        if (w == 0) {
+                            geom::Balls B;
+                            B.p4 = I.CP;
+                            B.N = N;
+                            B.has_extra = 0;
+                            B.tol = tol;
+                            B.skip = -1;
+                            B.lb = INFINITY;
+                            B.idx = nullptr;
+                            double x[3];
+                            int st = geom::lazy_exist(B, q, r, cw[e], SH.kp[0], SH.kid[0], x);
+                            if (ln == 0) {
+                                SH.status = st;
+                                SH.x[0] = x[0];
+                                SH.x[1] = x[1];
+                                SH.x[2] = x[2];
+                                atomicAdd(&I.counts[C_SEARCH], 1ull);
+                                if (st == geom::ST_NUMERIC) atomicAdd(&I.counts[C_NUMERIC], 1ull);
+                            }
+                        }
+                        __syncthreads();
+                        int st = SH.status;
+                        nw[0] = SH.x[0];
+                        nw[1] = SH.x[1];
+                        nw[2] = SH.x[2];
+                        __syncthreads();
+                        if (st != geom::ST_FOUND) continue;
+                    }
+                    // existing spheres whose witness lies in the new open (shrunk) ball
+                    nthr = threatened(I, N, q, r - tol, n, m, SH);
+                    revalidate(I, N, q, s, nthr, tol, SH, false);
+                    __syncthreads();
+                    int failed = SH.fail;
+                    __syncthreads();
+                    if (failed) continue;
+                    accepted = 1;
+                    val = s;
+                    kindv = ck[e];
+                    act = ct[e];
+                    wq[0] = nw[0];
+                    wq[1] = nw[1];
+                    wq[2] = nw[2];
+                    npend = 1;
+                }
+                if (!accepted) {
+                    if (lo <= tol && hi >= -tol) {
+                        val = 0.0;
+                        kindv = SDFI_KIND_ZERO;
+                        act = -1;
+                        accepted = 3;
+                    } else {
+                        int sigma = lo > tol ? 1 : -1;
+                        double rr, x[3];
+                        int64_t sph;
+                        int kk = blk::rmin_block<NW>(q, sigma, I.CP, I.CW, N, tol, tie, I.list, SH.kp, SH.kid, SH.S,
+                                                     &rr, x, &sph);
+                        if (kk > 0) {
+                            val = sigma * rr;
+                            kindv = kk == 1 ? SDFI_KIND_RMIN_T : (kk == 2 ? SDFI_KIND_RMIN_D : SDFI_KIND_RMIN_U);
+                            act = sph;
+                            wq[0] = x[0];
+                            wq[1] = x[1];
+                            wq[2] = x[2];
+                            accepted = 4;
+                            // Corollary 1: the minimal sphere covers no contour point; a cached
+                            // witness is only uncovered w.r.t. the shrunk balls and may sit just
+                            // inside the union, so witnesses inside the new ball are re-searched
+                            nthr = threatened(I, N, q, rr - tol, n, m, SH);
+                            revalidate(I, N, q, val, nthr, tol, SH, true);
+                            npend = 1;
+                        } else if (kk == 0) {
+                            val = 0.0;
+                            kindv = SDFI_KIND_ZERO;
+                            accepted = 3;
+                        } else {
+                            kindv = SDFI_KIND_UNRESOLVED;
+                        }
+                    }
+                }
+            }
+        }
+        // ---- record and append ----
+        __syncthreads();
+        if (npend) {
+            for (int64_t t = tid; t < nthr; t += GBS) {
+                int64_t c = I.list[t];
+                for (int jj = 0; jj < 3; ++jj) I.CW[3 * c + jj] = I.pend[3 * t + jj];
+            }
+        }
+        if (tid == 0) {
+            I.values[j] = val;
+            I.kind[j] = (uint8_t)kindv;
+            I.active[j] = act < 0 ? -1 : (act < n ? act : n + I.CSRC[act]);
+            I.order_out[k] = j;
+            int ci = kindv == SDFI_KIND_HI ? C_HI
+                   : kindv == SDFI_KIND_LO ? C_LO
+                   : kindv == SDFI_KIND_ZERO ? C_ZERO
+                   : kindv == SDFI_KIND_COINCIDENT ? C_COINC
+                   : kindv == SDFI_KIND_INFEASIBLE ? C_INFEAS
+                   : kindv == SDFI_KIND_UNRESOLVED ? C_UNRES : C_RMIN;
+            atomicAdd(&I.counts[ci], 1ull);
+            if (accepted) {
+                I.CP[4 * N] = q[0];
+                I.CP[4 * N + 1] = q[1];
+                I.CP[4 * N + 2] = q[2];
+                I.CP[4 * N + 3] = val;
+                I.CW[3 * N] = wq[0];
+                I.CW[3 * N + 1] = wq[1];
+                I.CW[3 * N + 2] = wq[2];
+                I.CSRC[N] = j;
+            } else {
+                I.witness[3 * j] = NAN;
+                I.witness[3 * j + 1] = NAN;
+                I.witness[3 * j + 2] = NAN;
+            }
+        }
+        if (accepted) ++N;
+        __threadfence_block();
+        __syncthreads();
+    }
+    // final witnesses of the query spheres and of the samples
+    for (int64_t c = n + tid; c < N; c += GBS) {
+        int64_t jq = I.CSRC[c];
+        for (int jj = 0; jj < 3; ++jj) I.witness[3 * jq + jj] = I.CW[3 * c + jj];
+    }
+    if (I.sample_witness)
+        for (int64_t c = tid; c < n; c += GBS)
+            for (int jj = 0; jj < 3; ++jj) I.sample_witness[3 * c + jj] = I.CW[3 * c + jj];
+}
+
+// one wavefront per sample: an uncovered point of its sphere, or none
+__global__ __launch_bounds__(256) void witness_kernel(const double *p4, int64_t n, double tol, double tie,
+                                                      double *wout, uint8_t *status) {
+    __shared__ geom::Cap kp[4][geom::KMAX];
+    __shared__ int64_t kid[4][geom::KMAX];
+    const int w = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    for (int64_t i = (int64_t)blockIdx.x * 4 + w; i < n; i += (int64_t)gridDim.x * 4) {
+        const double *pi = p4 + 4 * i;
+        int sg = blk::sign_class(pi[3], tie);
+        double sg1 = sg != 0 ? (double)sg : 1.0;
+        // hint: the neighbour e minimising sign(s_i) s_e + d_ie (towards the surface)
+        double best = INFINITY;
+        int64_t be = INT64_MAX;
+        for (int64_t e = ln; e < n; e += 64) {
+            if (e == i) continue;
+            double d = geom::dist3(pi, p4 + 4 * e);
+            if (!(d > 0.0)) continue;
+            double key = sg1 * p4[4 * e + 3] + d;
+            if (key < best) {
+                best = key;
+                be = e;
+            }
+        }
+        double g = geom::wmin(best);
+        int64_t cand = best == g ? be : INT64_MAX;
+        be = geom::wmin_i64(cand);
+        geom::Balls B;
+        B.p4 = p4;
+        B.N = n;
+        B.has_extra = 0;
+        B.tol = tol;
+        B.skip = i;
+        B.lb = INFINITY;
+        B.idx = nullptr;
+        double x[3];
+        int st = geom::lazy_exist(B, pi, fabs(pi[3]), be != INT64_MAX ? p4 + 4 * be : nullptr, kp[w], kid[w], x);
+        if (ln == 0) {
+            status[i] = st == geom::ST_FOUND ? 1 : 0;
+            for (int j = 0; j < 3; ++j) wout[3 * i + j] = st == geom::ST_FOUND ? x[j] : NAN;
+        }
+    }
+}
+
+struct GBufs {
+    double *CP, *CW, *pend, *win;
+    int64_t *CSRC, *list;
+    uint8_t *wstat;
+    unsigned long long *counts;
+    int64_t *order;
+    GInst *inst;
+};
+
+GBufs carve_greedy(Carver &c, int64_t n, int64_t m, int ninst) {
+    GBufs b;
+    int64_t cap = n + m + 1;
+    b.CP = c.take<double>(4 * cap);
+    b.CW = c.take<double>(3 * cap);
+    b.pend = c.take<double>(3 * cap);
+    b.win = c.take<double>(3 * (n + 1));
+    b.CSRC = c.take<int64_t>(cap);
+    b.list = c.take<int64_t>(2 * (cap + ninst) + 2);
+    b.wstat = c.take<uint8_t>(n + 1);
+    b.counts = c.take<unsigned long long>(C_NCOUNT * ninst);
+    b.order = c.take<int64_t>(m + 1);
+    b.inst = c.take<GInst>(ninst);
+    return b;
+}
+
+}  // namespace
+
+size_t witness_ws(int64_t, const sdfi_options &) { return 256; }
+
+sdfi_status run_witnesses(const double *samples, int64_t n, double *w, uint8_t *st, const sdfi_options &o,
+                          hipStream_t s) {
+    if (n == 0) return SDFI_OK;
+    int blocks = (int)std::min<int64_t>((n + 3) / 4, 4096);
+    KernelTimer tm("witness", s);
+    witness_kernel<<<blocks, 256, 0, s>>>(samples, n, o.tol, o.tie_tol, w, st);
+    tm.stop();
+    SDFI_HIP(hipGetLastError());
+    return SDFI_OK;
+}
+
+size_t greedy_ws(int64_t n, int64_t m, const sdfi_options &o) {
+    Carver c(nullptr, 0, true);
+    carve_greedy(c, n, m, 1);
+    Carver c2(nullptr, 0, true);
+    size_t ord = o.grid > 0 ? order_ws(n, m, o) : 0;
+    size_t cert = (o.flags & SDFI_OPT_CERTIFY) ? certify_ws(n + m, o) + 4 * (n + m) * 8 + 3 * (n + m) * 8 + 1024 : 0;
+    return c.used + std::max(ord, cert) + 1024;
+}
+
+sdfi_status run_order(const double *samples, int64_t n, const double *queries, int64_t m, int64_t *order_out,
+                      Carver &ws, const sdfi_options &o, hipStream_t st);
+
+static double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+__global__ void pack_set_kernel(const double *samples, int64_t n, const double *queries, const double *values,
+                                int64_t m, const double *sw, const double *qw, double *pv, double *wall) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) {
+        for (int j = 0; j < 4; ++j) pv[4 * i + j] = samples[4 * i + j];
+        for (int j = 0; j < 3; ++j) wall[3 * i + j] = sw[3 * i + j];
+    } else if (i < n + m) {
+        int64_t q = i - n;
+        for (int j = 0; j < 3; ++j) pv[4 * i + j] = queries[3 * q + j];
+        pv[4 * i + 3] = values[q];
+        for (int j = 0; j < 3; ++j) wall[3 * i + j] = qw[3 * q + j];
+    }
+}
+
+}  // namespace sdfi
+
+using namespace sdfi;
+
+extern "C" sdfi_status sdfi_sample_witnesses(const double *samples, int64_t n, double *witness_out,
+                                             uint8_t *status_out, void *, size_t, const sdfi_options *opt,
+                                             sdfi_stream stream) {
+    sdfi_options o;
+    sdfi_status s = read_options(opt, &o);
+    if (s != SDFI_OK) return s;
+    SDFI_CHECK_ARG(n >= 0 && n < (int64_t(1) << 31), "n out of range");
+    if (n == 0) return SDFI_OK;
+    SDFI_CHECK_ARG(samples && witness_out && status_out, "null array argument");
+    return run_witnesses(samples, n, witness_out, status_out, o, to_hip(stream));
+}
+
+static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *qoff, const int32_t *grids,
+                                 const double *samples, const double *queries, const int64_t *order_in,
+                                 double *values, int64_t *order_out, int64_t *active, uint8_t *kind, double *witness,
+                                 double *sample_witness, sdfi_report *report, void *ws, size_t ws_bytes,
+                                 const sdfi_options &o, hipStream_t st) {
+    const int64_t n = soff[ninst], m = qoff[ninst];
+    Carver c(ws, ws_bytes);
+    GBufs b = carve_greedy(c, n + ninst, m, ninst);
+    if (!c.ok()) {
+        set_error("workspace too small for the greedy interpolation");
+        return SDFI_ERR_WORKSPACE;
+    }
+    double t0 = now_ms();
+    // 1. witnesses of the input spheres
+    SDFI_HIP(hipMemsetAsync(b.wstat, 0, n + 1, st));
+    for (int i = 0; i < ninst; ++i) {
+        sdfi_status s = run_witnesses(samples + 4 * soff[i], soff[i + 1] - soff[i], b.win + 3 * soff[i],
+                                      b.wstat + soff[i], o, st);
+        if (s != SDFI_OK) return s;
+    }
+    if (o.flags & SDFI_OPT_INPUT_CHECK) {
+        std::vector<uint8_t> h(n);
+        SDFI_HIP(hipMemcpyAsync(h.data(), b.wstat, n, hipMemcpyDeviceToHost, st));
+        SDFI_HIP(hipStreamSynchronize(st));
+        for (int64_t i = 0; i < n; ++i)
+            if (!h[i]) {
+                set_error("input sample %lld has no uncovered point (Prop. 1 (ii) violated)", (long long)i);
+                return SDFI_ERR_INVALID_INPUT;
+            }
+    }
+    double t1 = now_ms();
+    // 2. order
+    const int64_t *ord = order_in;
+    if (!ord) {
+        for (int i = 0; i < ninst; ++i) {
+            sdfi_options oi = o;
+            oi.grid = grids ? grids[i] : o.grid;
+            if (oi.grid <= 0) {
+                set_error("order_in is NULL and no grid resolution was given");
+                return SDFI_ERR_INVALID_ARGUMENT;
+            }
+            Carver rest(c.base + c.used + 256, ws_bytes > c.used + 256 ? ws_bytes - c.used - 256 : 0);
+            sdfi_status s = run_order(samples + 4 * soff[i], soff[i + 1] - soff[i], nullptr, qoff[i + 1] - qoff[i],
+                                      b.order + qoff[i], rest, oi, st);
+            if (s != SDFI_OK) return s;
+        }
+        ord = b.order;
+    }
+    double t2 = now_ms();
+    // 3. greedy, one work-group per instance
+    std::vector<GInst> hi(ninst);
+    int64_t cpos = 0;
+    for (int i = 0; i < ninst; ++i) {
+        GInst &g = hi[i];
+        int64_t ni = soff[i + 1] - soff[i], mi = qoff[i + 1] - qoff[i];
+        g.samples = samples + 4 * soff[i];
+        g.queries = queries + 3 * qoff[i];
+        g.order = ord + qoff[i];
+        g.w_in = b.win + 3 * soff[i];
+        g.values = values + qoff[i];
+        g.active = active + qoff[i];
+        g.kind = kind + qoff[i];
+        g.witness = witness + 3 * qoff[i];
+        g.sample_witness = sample_witness ? sample_witness + 3 * soff[i] : nullptr;
+        g.order_out = order_out + qoff[i];
+        g.CP = b.CP + 4 * cpos;
+        g.CW = b.CW + 3 * cpos;
+        g.pend = b.pend + 3 * cpos;
+        g.CSRC = b.CSRC + cpos;
+        g.list = b.list + 2 * (cpos + i);
+        g.counts = b.counts + C_NCOUNT * i;
+        g.n = ni;
+        g.m = mi;
+        cpos += ni + mi;
+    }
+    SDFI_HIP(hipMemcpyAsync(b.inst, hi.data(), sizeof(GInst) * ninst, hipMemcpyHostToDevice, st));
+    KernelTimer tm("greedy", st);
+    greedy_kernel<<<ninst, GBS, 0, st>>>(b.inst, o.tol, o.tie_tol, o.domain_lo[0], o.domain_lo[1], o.domain_lo[2],
+                                         o.domain_hi[0], o.domain_hi[1], o.domain_hi[2]);
+    tm.stop();
+    SDFI_HIP(hipGetLastError());
+    std::vector<unsigned long long> cnt(C_NCOUNT * ninst);
+    SDFI_HIP(hipMemcpyAsync(cnt.data(), b.counts, sizeof(unsigned long long) * cnt.size(), hipMemcpyDeviceToHost, st));
+    SDFI_HIP(hipStreamSynchronize(st));
+    double t3 = now_ms();
+    if (report) {
+        std::memset(report, 0, sizeof(*report));
+        int64_t pairs = 0;
+        for (int i = 0; i < ninst; ++i) {
+            int64_t ni = soff[i + 1] - soff[i], mi = qoff[i + 1] - qoff[i];
+            pairs += mi * ni + mi * (mi - 1) / 2;
+            const unsigned long long *cc = cnt.data() + C_NCOUNT * i;
+            report->n_hi += cc[C_HI];
+            report->n_lo += cc[C_LO];
+            report->n_zero += cc[C_ZERO];
+            report->n_rmin += cc[C_RMIN];
+            report->n_coincident += cc[C_COINC];
+            report->n_infeasible += cc[C_INFEAS];
+            report->n_unresolved += cc[C_UNRES];
+            report->n_exact_searches += cc[C_SEARCH];
+            report->n_fp64_rechecks += cc[C_NUMERIC];
+        }
+        report->pairs_evaluated = pairs;
+        report->ms_phase[0] = t2 - t1;
+        report->ms_phase[1] = t1 - t0;
+        report->ms_phase[2] = t3 - t2;
+    }
+    // 4. optional certificate of each instance's final set
+    if (o.flags & SDFI_OPT_CERTIFY) {
+        int64_t pv_tot = 0, wv_tot = 0;
+        for (int i = 0; i < ninst; ++i) {
+            int64_t ni = soff[i + 1] - soff[i], mi = qoff[i + 1] - qoff[i];
+            Carver cc2(c.base + c.used + 256, ws_bytes > c.used + 256 ? ws_bytes - c.used - 256 : 0);
+            double *pvb = cc2.take<double>(4 * (ni + mi));
+            double *wb = cc2.take<double>(3 * (ni + mi));
+            if (!cc2.ok()) {
+                set_error("workspace too small for the certificate");
+                return SDFI_ERR_WORKSPACE;
+            }
+            const double *sw = sample_witness ? sample_witness + 3 * soff[i] : b.win + 3 * soff[i];
+            pack_set_kernel<<<(unsigned)((ni + mi + 255) / 256), 256, 0, st>>>(
+                samples + 4 * soff[i], ni, queries + 3 * qoff[i], values + qoff[i], mi, sw, witness + 3 * qoff[i],
+                pvb, wb);
+            int64_t pv = 0, wv = 0;
+            sdfi_status s = run_certify(pvb, wb, ni + mi, &pv, &wv, cc2, o, st);
+            if (s != SDFI_OK) return s;
+            pv_tot += pv;
+            wv_tot += wv;
+        }
+        if (report) {
+            report->n_violations_pairwise = pv_tot;
+            report->n_violations_witness = wv_tot;
+            report->ms_phase[3] = now_ms() - t3;
+        }
+    }
+    return SDFI_OK;
+}
+
+extern "C" sdfi_status sdfi_greedy_interpolate(const double *samples, int64_t n, const double *queries, int64_t m,
+                                               const int64_t *order_in, double *values, int64_t *order_out,
+                                               int64_t *active, uint8_t *kind, double *witness,
+                                               double *sample_witness, sdfi_report *report, void *ws,
+                                               size_t ws_bytes, const sdfi_options *opt, sdfi_stream stream) {
+    sdfi_options o;
+    sdfi_status s = read_options(opt, &o);
+    if (s != SDFI_OK) return s;
+    SDFI_CHECK_ARG(n >= 1 && m >= 0 && n + m < (int64_t(1) << 31), "sizes out of range");
+    if (m == 0) return SDFI_OK;
+    SDFI_CHECK_ARG(samples && queries && values && order_out && active && kind && witness, "null array argument");
+    SDFI_CHECK_ARG(order_in || o.grid > 0, "order_in is NULL and opt->grid is 0");
+    if (o.grid > 0 && !order_in)
+        SDFI_CHECK_ARG((int64_t)o.grid * o.grid * o.grid == n && m == 8 * n,
+                       "grid %d needs n = grid^3 samples and m = 8 n refinement queries", o.grid);
+    if (ws_bytes < greedy_ws(n, m, o) || !ws) {
+        set_error("workspace of %zu bytes is below the %zu required", ws_bytes, greedy_ws(n, m, o));
+        return SDFI_ERR_WORKSPACE;
+    }
+    int64_t soff[2] = {0, n}, qoff[2] = {0, m};
+    int32_t g = o.grid;
+    return greedy_common(1, soff, qoff, &g, samples, queries, order_in, values, order_out, active, kind, witness,
+                         sample_witness, report, ws, ws_bytes, o, to_hip(stream));
+}
+
+extern "C" sdfi_status sdfi_greedy_interpolate_batched(int32_t num_instances, const int64_t *sample_offsets,
+                                                       const int64_t *query_offsets, const int32_t *grids,
+                                                       const double *samples, const double *queries, double *values,
+                                                       int64_t *order_out, int64_t *active, uint8_t *kind,
+                                                       double *witness, sdfi_report *report, void *ws,
+                                                       size_t ws_bytes, const sdfi_options *opt, sdfi_stream stream) {
+    sdfi_options o;
+    sdfi_status s = read_options(opt, &o);
+    if (s != SDFI_OK) return s;
+    SDFI_CHECK_ARG(num_instances >= 1 && num_instances <= 65535, "num_instances out of range");
+    SDFI_CHECK_ARG(sample_offsets && query_offsets && grids, "null host offset/grid array");
+    SDFI_CHECK_ARG(sample_offsets[0] == 0 && query_offsets[0] == 0, "offsets must start at 0");
+    for (int i = 0; i < num_instances; ++i) {
+        int64_t ni = sample_offsets[i + 1] - sample_offsets[i], mi = query_offsets[i + 1] - query_offsets[i];
+        SDFI_CHECK_ARG(grids[i] > 0 && (int64_t)grids[i] * grids[i] * grids[i] == ni && mi == 8 * ni,
+                       "instance %d: grid %d needs grid^3 samples and 8x as many queries", i, grids[i]);
+    }
+    const int64_t n = sample_offsets[num_instances], m = query_offsets[num_instances];
+    SDFI_CHECK_ARG(n + m < (int64_t(1) << 31), "total size out of range");
+    SDFI_CHECK_ARG(samples && queries && values && order_out && active && kind && witness, "null array argument");
+    size_t need = greedy_ws(n + num_instances, m, o);
+    if (ws_bytes < need || !ws) {
+        set_error("workspace of %zu bytes is below the %zu required", ws_bytes, need);
+        return SDFI_ERR_WORKSPACE;
+    }
+    return greedy_common(num_instances, sample_offsets, query_offsets, grids, samples, queries, nullptr, values,
+                         order_out, active, kind, witness, nullptr, report, ws, ws_bytes, o, to_hip(stream));
+}

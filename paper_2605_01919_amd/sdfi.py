@@ -71,7 +71,8 @@ def lib():
     return _lib
 
 
-EXPORTS = ["sdfi_default_options", "sdfi_last_error", "sdfi_version", "sdfi_workspace_size", "sdfi_bounds",
+EXPORTS = ["sdfi_default_options", "sdfi_last_error", "sdfi_version", "sdfi_timing_enable", "sdfi_timing_query",
+           "sdfi_timing_reset", "sdfi_workspace_size", "sdfi_bounds",
            "sdfi_certify", "sdfi_refinement_order", "sdfi_sample_witnesses", "sdfi_greedy_interpolate",
            "sdfi_greedy_interpolate_batched", "sdfi_min_valid_radius", "sdfi_repair", "sdfi_greedy_backward"]
 
@@ -108,9 +109,29 @@ def _dev(t, dtype, shape_last=None, name="tensor"):
         raise SdfiError(f"{name} must be a GPU tensor")
     if t.dtype != dtype:
         raise SdfiError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape_last is None and t.dim() != 1:
+        raise SdfiError(f"{name} must be one-dimensional, got {tuple(t.shape)}")
     if shape_last is not None and (t.dim() != 2 or t.shape[1] != shape_last):
         raise SdfiError(f"{name} must have shape (k, {shape_last}), got {tuple(t.shape)}")
     return t.contiguous()
+
+
+def timing(on=True):
+    """Enable or disable the library's kernel timing (HIP events on the caller's stream)."""
+    if on:
+        lib().sdfi_timing_reset()
+    lib().sdfi_timing_enable(1 if on else 0)
+
+
+def timing_read(names=("sweep", "resolve", "certify", "greedy", "witness", "rmin")):
+    """{name: (total ms, launches)} recorded since timing() was enabled."""
+    out = {}
+    for nm in names:
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        _check(lib().sdfi_timing_query(nm.encode(), ctypes.byref(ms), ctypes.byref(cnt)), "sdfi_timing_query")
+        out[nm] = (ms.value, cnt.value)
+    return out
 
 
 def workspace(op, n, m, opt):
@@ -149,3 +170,173 @@ def certify(pts_values, witness):
                               ctypes.c_size_t(ws.numel()), ctypes.byref(opt), _stream()), "sdfi_certify")
     return {"pair": rep.n_violations_pairwise, "witness": rep.n_violations_witness,
             "pairs_evaluated": rep.pairs_evaluated}
+
+
+def refinement_order(samples, grid, queries=None):
+    """Refinement order (int64 query indices)."""
+    samples = _dev(samples, torch.float64, 4, "samples")
+    n = samples.shape[0]
+    m = 8 * n if queries is None else queries.shape[0]
+    if queries is not None:
+        queries = _dev(queries, torch.float64, 3, "queries")
+    opt = options(grid=grid)
+    out = torch.empty(m, dtype=torch.int64, device=samples.device)
+    ws = workspace(OP_ORDER, n, m, opt)
+    _check(lib().sdfi_refinement_order(_ptr(samples), ctypes.c_int64(n), _ptr(queries), ctypes.c_int64(m),
+                                       _ptr(out), _ptr(ws), ctypes.c_size_t(ws.numel()), ctypes.byref(opt),
+                                       _stream()), "sdfi_refinement_order")
+    return out
+
+
+def sample_witnesses(samples):
+    samples = _dev(samples, torch.float64, 4, "samples")
+    n = samples.shape[0]
+    opt = options()
+    w = torch.empty((n, 3), dtype=torch.float64, device=samples.device)
+    st = torch.empty(n, dtype=torch.uint8, device=samples.device)
+    ws = workspace(OP_WITNESS, n, 0, opt)
+    _check(lib().sdfi_sample_witnesses(_ptr(samples), ctypes.c_int64(n), _ptr(w), _ptr(st), _ptr(ws),
+                                       ctypes.c_size_t(ws.numel()), ctypes.byref(opt), _stream()),
+           "sdfi_sample_witnesses")
+    return w, st
+
+
+def greedy(samples, queries, order=None, grid=0, certify=False, input_check=False, sample_witness=False):
+    """Greedy interpolation.  Returns a dict of GPU tensors and the host report."""
+    samples = _dev(samples, torch.float64, 4, "samples")
+    queries = _dev(queries, torch.float64, 3, "queries")
+    n, m = samples.shape[0], queries.shape[0]
+    flags = (OPT_CERTIFY if certify else 0) | (OPT_INPUT_CHECK if input_check else 0)
+    opt = options(grid=grid, flags=flags)
+    dev = samples.device
+    if order is not None:
+        order = _dev(order, torch.int64, None, "order")
+    out = {
+        "values": torch.empty(m, dtype=torch.float64, device=dev),
+        "order": torch.empty(m, dtype=torch.int64, device=dev),
+        "active": torch.empty(m, dtype=torch.int64, device=dev),
+        "kind": torch.empty(m, dtype=torch.uint8, device=dev),
+        "witness": torch.empty((m, 3), dtype=torch.float64, device=dev),
+        "sample_witness": torch.empty((n, 3), dtype=torch.float64, device=dev) if sample_witness else None,
+    }
+    rep = Report()
+    ws = workspace(OP_GREEDY, n, m, opt)
+    _check(lib().sdfi_greedy_interpolate(
+        _ptr(samples), ctypes.c_int64(n), _ptr(queries), ctypes.c_int64(m), _ptr(order), _ptr(out["values"]),
+        _ptr(out["order"]), _ptr(out["active"]), _ptr(out["kind"]), _ptr(out["witness"]),
+        _ptr(out["sample_witness"]), ctypes.byref(rep), _ptr(ws), ctypes.c_size_t(ws.numel()), ctypes.byref(opt),
+        _stream()), "sdfi_greedy_interpolate")
+    out["report"] = rep.as_dict()
+    return out
+
+
+def greedy_batched(instances, certify=False):
+    """instances: list of (samples (n_i,4), queries (8 n_i,3), grid_i) GPU tensors."""
+    soff = [0]
+    qoff = [0]
+    for s, q, g in instances:
+        soff.append(soff[-1] + s.shape[0])
+        qoff.append(qoff[-1] + q.shape[0])
+    samples = torch.cat([_dev(s, torch.float64, 4, "samples") for s, _, _ in instances])
+    queries = torch.cat([_dev(q, torch.float64, 3, "queries") for _, q, _ in instances])
+    grids = (ctypes.c_int32 * len(instances))(*[int(g) for _, _, g in instances])
+    so = (ctypes.c_int64 * len(soff))(*soff)
+    qo = (ctypes.c_int64 * len(qoff))(*qoff)
+    n, m = soff[-1], qoff[-1]
+    opt = options(flags=OPT_CERTIFY if certify else 0)
+    dev = samples.device
+    out = {
+        "values": torch.empty(m, dtype=torch.float64, device=dev),
+        "order": torch.empty(m, dtype=torch.int64, device=dev),
+        "active": torch.empty(m, dtype=torch.int64, device=dev),
+        "kind": torch.empty(m, dtype=torch.uint8, device=dev),
+        "witness": torch.empty((m, 3), dtype=torch.float64, device=dev),
+        "sample_offsets": soff, "query_offsets": qoff,
+    }
+    rep = Report()
+    ws = workspace(OP_GREEDY, n + len(instances), m, opt)
+    _check(lib().sdfi_greedy_interpolate_batched(
+        ctypes.c_int32(len(instances)), so, qo, grids, _ptr(samples), _ptr(queries), _ptr(out["values"]),
+        _ptr(out["order"]), _ptr(out["active"]), _ptr(out["kind"]), _ptr(out["witness"]), ctypes.byref(rep),
+        _ptr(ws), ctypes.c_size_t(ws.numel()), ctypes.byref(opt), _stream()), "sdfi_greedy_interpolate_batched")
+    out["report"] = rep.as_dict()
+    return out
+
+
+def min_valid_radius(samples, queries):
+    """Minimum valid radius (sign by containment) of each query point."""
+    samples = _dev(samples, torch.float64, 4, "samples")
+    queries = _dev(queries, torch.float64, 3, "queries")
+    n, m = samples.shape[0], queries.shape[0]
+    opt = options()
+    dev = samples.device
+    val = torch.empty(m, dtype=torch.float64, device=dev)
+    kind = torch.empty(m, dtype=torch.uint8, device=dev)
+    wit = torch.empty((m, 3), dtype=torch.float64, device=dev)
+    ws = workspace(OP_RMIN, n, m, opt)
+    _check(lib().sdfi_min_valid_radius(_ptr(samples), ctypes.c_int64(n), _ptr(queries), ctypes.c_int64(m),
+                                       _ptr(val), _ptr(kind), _ptr(wit), _ptr(ws), ctypes.c_size_t(ws.numel()),
+                                       ctypes.byref(opt), _stream()), "sdfi_min_valid_radius")
+    return val, kind, wit
+
+
+def repair(samples, queries=None):
+    """Pseudo-SDF repair.  Returns (repaired values, removed mask, query values, kinds, report)."""
+    samples = _dev(samples, torch.float64, 4, "samples")
+    dev = samples.device
+    if queries is None:
+        queries = torch.zeros((0, 3), dtype=torch.float64, device=dev)
+    queries = _dev(queries, torch.float64, 3, "queries")
+    n, m = samples.shape[0], queries.shape[0]
+    opt = options()
+    rep_v = torch.empty(n, dtype=torch.float64, device=dev)
+    removed = torch.empty(n, dtype=torch.uint8, device=dev)
+    qv = torch.empty(max(m, 1), dtype=torch.float64, device=dev)
+    kind = torch.empty(n + m, dtype=torch.uint8, device=dev)
+    rep = Report()
+    ws = workspace(OP_REPAIR, n, m, opt)
+    _check(lib().sdfi_repair(_ptr(samples), ctypes.c_int64(n), _ptr(queries), ctypes.c_int64(m), _ptr(rep_v),
+                             _ptr(removed), _ptr(qv), _ptr(kind), ctypes.byref(rep), _ptr(ws),
+                             ctypes.c_size_t(ws.numel()), ctypes.byref(opt), _stream()), "sdfi_repair")
+    return rep_v, removed, qv[:m], kind, rep.as_dict()
+
+
+def greedy_backward(grad_values, samples, queries, values, active, kind):
+    """d(sum grad_values * values)/d(sample values, sample positions)."""
+    samples = _dev(samples, torch.float64, 4, "samples")
+    queries = _dev(queries, torch.float64, 3, "queries")
+    grad_values = _dev(grad_values, torch.float64, None, "grad_values")
+    values = _dev(values, torch.float64, None, "values")
+    active = _dev(active, torch.int64, None, "active")
+    kind = _dev(kind, torch.uint8, None, "kind")
+    n, m = samples.shape[0], queries.shape[0]
+    gs = torch.empty(n, dtype=torch.float64, device=samples.device)
+    gp = torch.empty((n, 3), dtype=torch.float64, device=samples.device)
+    ws = workspace(OP_BACKWARD, n, m, options())
+    _check(lib().sdfi_greedy_backward(_ptr(grad_values), _ptr(samples), ctypes.c_int64(n), _ptr(queries),
+                                      ctypes.c_int64(m), _ptr(values), _ptr(active), _ptr(kind), _ptr(gs), _ptr(gp),
+                                      _ptr(ws), ctypes.c_size_t(ws.numel()), _stream()), "sdfi_greedy_backward")
+    return gs, gp
+
+
+class GreedyInterpolate(torch.autograd.Function):
+    """values = greedy interpolation of `queries` from samples (points, values).
+
+    Forward runs sdfi_greedy_interpolate; backward runs sdfi_greedy_backward,
+    the adjoint through each value's active parent (decisions held fixed).
+    Gradients flow to the sample positions (n, 3) and values (n,).
+    """
+
+    @staticmethod
+    def forward(ctx, points, values, queries, grid=0, order=None):
+        samples = torch.cat([points.detach(), values.detach()[:, None]], dim=1).contiguous()
+        out = greedy(samples, queries.detach(), order=order, grid=grid)
+        ctx.save_for_backward(samples, queries.detach(), out["values"], out["active"], out["kind"])
+        ctx.mark_non_differentiable(out["kind"], out["active"])
+        return out["values"], out["kind"], out["active"]
+
+    @staticmethod
+    def backward(ctx, gv, _gk=None, _ga=None):
+        samples, queries, values, active, kind = ctx.saved_tensors
+        gs, gp = greedy_backward(gv.contiguous().to(torch.float64), samples, queries, values, active, kind)
+        return gp, gs, None, None, None

@@ -1,0 +1,121 @@
+"""GPU parity of the greedy interpolation, its order and the sample witnesses
+against the oracle (Sec. 3.3, Sec. 4, Prop. 1, Prop. 2)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import certify as OC
+from oracle import greedy as OG
+from oracle import order as OO
+from oracle.common import KIND_HI, KIND_LO, TOL, dist
+from paper_2605_01919_amd import sdfi
+from sdfgen import configs
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+CASES = {
+    "sphere4": lambda: configs.sphere(4),
+    "sphere5": lambda: configs.sphere(5),
+    "sphere6": lambda: configs.sphere(6),
+    "balls5": lambda: configs.ball_union(5),
+    "balls6": lambda: configs.ball_union(6),
+}
+
+
+@pytest.mark.parametrize("name", ["sphere4", "sphere6", "balls6"])
+def test_order_matches_oracle(name):
+    w = CASES[name]()
+    print("order", name, flush=True)
+    got = sdfi.refinement_order(dev(np.c_[w.points, w.values]), w.grid).cpu().numpy()
+    want, _, _ = OO.refinement_order(w.points, w.values, w.grid)
+    np.testing.assert_array_equal(got, want)
+
+
+def test_sample_witnesses_are_witnesses():
+    w = configs.sphere(8)
+    W, st = sdfi.sample_witnesses(dev(np.c_[w.points, w.values]))
+    W, st = W.cpu().numpy(), st.cpu().numpy()
+    assert st.all()
+    # on their sphere and covered by no other ball
+    assert np.all(np.abs(dist(W, w.points) - np.abs(w.values)) <= TOL)
+    for i in range(0, w.n, 7):
+        d = dist(w.points, W[i])
+        cov = d < np.abs(w.values) - TOL
+        cov[i] = False
+        assert not cov.any()
+    # a sphere inside another ball has none
+    P = np.array([[0.0, 0, 0], [0.05, 0, 0], [0.5, 0.5, 0.5]])
+    S = np.array([0.3, 0.1, 0.1])
+    _, st2 = sdfi.sample_witnesses(dev(np.c_[P, S]))
+    assert st2.cpu().numpy().tolist() == [1, 0, 1]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_greedy_matches_oracle(name):
+    w = CASES[name]()
+    print("greedy", name, w.n, w.m, flush=True)
+    g = sdfi.greedy(dev(np.c_[w.points, w.values]), dev(w.queries), grid=w.grid, certify=True, sample_witness=True)
+    torch.cuda.synchronize()
+    rep = g["report"]
+    print("report", rep, flush=True)
+    W, ok = OG.input_witnesses(w.points, w.values)
+    order, _, _ = OO.refinement_order(w.points, w.values, w.grid)
+    r = OG.greedy_interpolate(w.points, w.values, w.queries, order, W)
+    np.testing.assert_array_equal(g["order"].cpu().numpy(), order)
+    vals = g["values"].cpu().numpy()
+    kinds = g["kind"].cpu().numpy()
+    act = g["active"].cpu().numpy()
+    # a contact point that is both the nearest point of an intersection circle
+    # (D) and an arc end on it (U) carries either label: compare D/U as one class
+    kc = np.where(kinds == 6, 5, kinds)
+    ko = np.where(r.kind == 6, 5, r.kind)
+    mism = np.nonzero(kc != ko)[0]
+    if len(mism):
+        first = min(mism, key=lambda j: np.nonzero(order == j)[0][0])
+        print("first kind mismatch at query", first, "step", int(np.nonzero(order == first)[0][0]),
+              "gpu", kinds[first], vals[first], "oracle", r.kind[first], r.values[first], flush=True)
+    np.testing.assert_array_equal(kc, ko)
+    np.testing.assert_allclose(vals, r.values, rtol=0, atol=1e-5)
+    single = np.isin(r.kind, [KIND_HI, KIND_LO, 7])
+    np.testing.assert_array_equal(act[single], r.active[single])
+    assert np.all(np.sign(vals) == np.sign(r.values))
+    # the GPU output certifies, on the GPU and in the oracle (independent checker)
+    P = np.vstack([w.points, w.queries])
+    S = np.concatenate([w.values, vals])
+    Wt = np.vstack([g["sample_witness"].cpu().numpy(), g["witness"].cpu().numpy()])
+    cert = OC.certify(P, S, Wt)
+    if cert["violations"]:
+        R = np.abs(S)
+        kall = np.concatenate([np.zeros(w.n, int), kinds])
+        step = np.full(len(S), -1)
+        step[w.n + order] = np.arange(w.m)
+        for i in range(len(S)):
+            dw = dist(P, Wt[i])
+            cov = dw < R - TOL - 1e-9
+            cov[i] = False
+            for c in np.nonzero(cov)[0][:3]:
+                print("witness of", i, "kind", kall[i], "step", step[i], "covered by", c, "kind", kall[c], "step",
+                      step[c], "margin", R[c] - TOL - dw[c], flush=True)
+    assert cert["violations"] == 0, cert
+    assert rep["n_violations_pairwise"] == 0 and rep["n_violations_witness"] == 0
+
+
+def test_greedy_runs_twice_identically():
+    w = configs.ball_union(5)
+    a = sdfi.greedy(dev(np.c_[w.points, w.values]), dev(w.queries), grid=w.grid)
+    b = sdfi.greedy(dev(np.c_[w.points, w.values]), dev(w.queries), grid=w.grid)
+    assert torch.equal(a["values"], b["values"]) and torch.equal(a["kind"], b["kind"])
+    assert torch.equal(a["active"], b["active"])
+
+
+def test_input_check_rejects_covered_sample():
+    P = np.array([[0.2, 0.2, 0.2], [0.22, 0.2, 0.2], [0.6, 0.6, 0.6]])
+    S = np.array([0.15, 0.05, 0.1])
+    Q = np.array([[0.5, 0.5, 0.5]])
+    with pytest.raises(sdfi.SdfiError, match="status 4"):
+        sdfi.greedy(dev(np.c_[P, S]), dev(Q), order=dev(np.array([0]), torch.int64), input_check=True)
