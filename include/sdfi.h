@@ -107,6 +107,8 @@ typedef struct {
     int64_t n_violations_pairwise; /* certificate: pairs breaking the cone */
     int64_t n_violations_witness;  /* certificate: witnesses off their sphere or covered */
     int64_t n_removed;             /* repair: fully covered samples removed */
+    int64_t n_search_capped;       /* exact searches that hit their work cap (candidate rejected or
+                                      query UNRESOLVED; never an unproven acceptance) */
     double ms_phase[8];            /* wall time per phase, see each entry point */
 } sdfi_report;
 

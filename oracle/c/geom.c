@@ -331,10 +331,11 @@ static int cmp_lb(const void *x, const void *y)
 
 /* Minimum valid radius of a query q of sign sigma: the distance from q to
  * the contour of the union of sigma-balls (proof of Prop. 2).  The contour is
- * that of the balls themselves (no tolerance in the geometry), so the
- * contact point lies outside every tolerance-shrunk ball with margin tol and
- * the new sphere keeps an uncovered neighbourhood there.  q counts as inside
- * a ball when d < |s| - tol.  Returns the
+ * that of the balls shrunk by the uniqueness tolerance `tie` only (not by
+ * tol), so the contact point lies outside every tol-shrunk ball with margin
+ * tol - tie and the new sphere keeps an uncovered neighbourhood there, while
+ * exactly tangent spheres still leave non-degenerate gaps.  q counts as
+ * inside a ball when d < |s| - tol.  Returns the
  * kind of the nearest contour point (0: q in no sigma-ball, radius 0;
  * 1 T, 2 D, 3 U; -1 nothing found).  W (nullable, NaN rows allowed) holds
  * known uncovered points; the nearest one on a sigma-sphere bounds the
@@ -392,7 +393,7 @@ int og_min_valid_radius(const double *q, int sigma, const double *P, const doubl
     }
     int kind = 0;
     double y[3], d;
-    int kk = og_nearest_uncovered(P + 3 * deepest, fabs(S[deepest]), LPc, LSc, LN, q, bound, 0.0, &d, y);
+    int kk = og_nearest_uncovered(P + 3 * deepest, fabs(S[deepest]), LPc, LSc, LN, q, bound, tie, &d, y);
     if (kk) {
         bound = d; kind = kk; *sphere = deepest;
         x[0] = y[0]; x[1] = y[1]; x[2] = y[2];
@@ -408,7 +409,7 @@ int og_min_valid_radius(const double *q, int sigma, const double *P, const doubl
         if (ord[k].lb >= bound) break;
         long i = ord[k].idx;
         if (i == deepest) continue;
-        kk = og_nearest_uncovered(P + 3 * i, fabs(S[i]), LPc, LSc, LN, q, bound, 0.0, &d, y);
+        kk = og_nearest_uncovered(P + 3 * i, fabs(S[i]), LPc, LSc, LN, q, bound, tie, &d, y);
         if (kk && d < bound) {
             bound = d; kind = kk; *sphere = i;
             x[0] = y[0]; x[1] = y[1]; x[2] = y[2];

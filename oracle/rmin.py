@@ -15,10 +15,12 @@ by the lower bound |d_i - |s_i||, stopping when the bound exceeds the best
 found.  Candidates on opposite-sign spheres are never nearer than the contour
 (the sigma-contour is separated from the other sign), so only sigma-spheres
 are searched.  Coverage is tested against every ball, as the paper's
-point_uncovered does.  The contour is that of the balls themselves (no
-tolerance in this geometry): the contact point then lies outside every
-tolerance-shrunk ball with margin TOL, so the new sphere keeps an uncovered
-neighbourhood there; only "q is inside a ball" uses d < |s| - TOL.
+point_uncovered does.  The contour is that of the balls shrunk by the
+uniqueness tolerance TIE_TOL only (1e-9, Appendix B), not by TOL: the
+contact point then lies outside every TOL-shrunk ball with margin
+TOL - TIE_TOL, so the new sphere keeps an uncovered neighbourhood there,
+and exactly tangent spheres (which the greedy produces all the time) still
+leave non-degenerate gaps.  "q is inside a ball" uses d < |s| - TOL.
 """
 from __future__ import annotations
 
@@ -59,7 +61,7 @@ def min_valid_radius(q, sigma, P, S, tol=TOL, W=None):
     # when uncovered (no contour point lies closer than max_i(|s_i| - d_i))
     depth = R[mine] - d[mine]
     deepest = mine[int(np.argmax(depth))]
-    res = nearest_uncovered(P[deepest], R[deepest], P, S, q, best, 0.0)
+    res = nearest_uncovered(P[deepest], R[deepest], P, S, q, best, TIE_TOL)
     if res is not None:
         best = res[0]
         out = (res[0], res[1], res[2], int(deepest))
@@ -72,7 +74,7 @@ def min_valid_radius(q, sigma, P, S, tol=TOL, W=None):
             break
         if i == deepest:
             continue
-        res = nearest_uncovered(P[i], R[i], P, S, q, best, 0.0)
+        res = nearest_uncovered(P[i], R[i], P, S, q, best, TIE_TOL)
         if res is not None and res[0] < best:
             best = res[0]
             out = (res[0], res[1], res[2], i)

@@ -87,7 +87,7 @@ __global__ void scatter_kernel(const double *G, const int64_t *active, const uin
     int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (j >= m) return;
     int64_t t = active[j];
-    if (t < 0 || t >= n || ds[j] == 0.0 && dp[3 * j] == 0.0 && dp[3 * j + 1] == 0.0 && dp[3 * j + 2] == 0.0) return;
+    if (t < 0 || t >= n || (ds[j] == 0.0 && dp[3 * j] == 0.0 && dp[3 * j + 1] == 0.0 && dp[3 * j + 2] == 0.0)) return;
     int k = kind[j];
     if (!(k == SDFI_KIND_HI || k == SDFI_KIND_LO || k == SDFI_KIND_COINCIDENT || k == SDFI_KIND_RMIN_T)) return;
     double g = G[j];

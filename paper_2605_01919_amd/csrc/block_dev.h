@@ -24,6 +24,7 @@ struct Shared {
     int wnd[NW];
     double wx[NW][3];
     unsigned long long bound_bits;
+    double wlow[NW];
 };
 
 __device__ inline int wid() { return threadIdx.x >> 6; }
@@ -103,10 +104,11 @@ __device__ inline bool better(double d, int nd, double lb, int64_t i, double d2,
 
 // Minimum valid radius of q for sign sigma against balls rows [0, N) of p4
 // (x, y, z, s) with known uncovered points W (rows may be NaN).  The contour
-// is that of the balls themselves (no tolerance in the geometry), so the
-// contact point clears every tolerance-shrunk ball; q counts as inside a ball
-// when d < |s| - tol.  Returns kind 0 (q in no sigma ball: radius 0),
-// 1 T, 2 D, 3 U, -1 nothing found.  list: scratch of 2 (N + 1) entries;
+// is that of the balls shrunk by the uniqueness tolerance `tie` only, so the
+// contact point clears every tol-shrunk ball by tol - tie while exactly
+// tangent spheres leave non-degenerate gaps; q counts as inside a ball when
+// d < |s| - tol.  Returns kind 0 (q in no sigma ball: radius 0),
+// 1 T, 2 D, 3 U, -1 nothing found, -2 a search hit its cap (no answer).  list: scratch of 2 (N + 1) entries;
 // kp/kid: per wave LDS scratch.
 template <int NW>
 __device__ inline int rmin_block(const double *q, int sigma, const double *p4, const double *W, int64_t N, double tol,
@@ -169,12 +171,13 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
         L.N = nl;
         L.idx = lset;
         L.has_extra = 0;
-        L.tol = 0.0;
+        L.tol = tie;  // contour of the balls shrunk by the uniqueness tolerance only
         L.skip = -1;
         L.lq[0] = q[0];
         L.lq[1] = q[1];
         L.lq[2] = q[2];
         L.lb = INFINITY;  // already applied by the index list
+        L.use_region = 0;
         if (tid == 0) {
             S.counter = 0;
             S.bound_bits = __double_as_longlong(bound);
@@ -184,6 +187,7 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
         double wd = INFINITY, wlb = INFINITY, wx[3] = {0.0, 0.0, 0.0};
         int64_t wi = INT64_MAX;
         int wk = 0, wnd = 1;
+        double wlow = INFINITY;
         const int w = wid();
         for (int guard = 0; guard < (1 << 30); ++guard) {
             int k = 0;
@@ -196,9 +200,17 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
             unsigned long long cb = 0;
             if (lane() == 0) cb = __hip_atomic_load(&S.bound_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             double cur = __longlong_as_double((long long)__shfl(cb, 0, 64));  // wave-uniform
-            if (lbi > cur) continue;
+            // prune only clearly worse spheres: exact ties must reach the tie-break
+            if (lbi > cur * (1.0 + 1e-12) + 1e-15) continue;
             double d, x[3];
-            int kk = geom::lazy_nearest(L, p, fabs(p[3]), q, cur, kp[w], kid[w], &d, x);
+            int kk = geom::lazy_nearest(L, p, fabs(p[3]), q, cur * (1.0 + 1e-12) + 1e-15, kp[w], kid[w], &d, x);
+            if (kk < 0) {
+                // a capped search proved only that this sphere has no uncovered
+                // point nearer than d (a lower bound); it matters only if the
+                // final answer is farther than that
+                wlow = fmin(wlow, d);
+                continue;
+            }
             if (kk && better(d, i != deepest, lbi, i, wd, wnd, wlb, wi)) {
                 wd = d;
                 wnd = i != deepest;
@@ -213,6 +225,7 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
             }
         }
         if (lane() == 0) {
+            S.wlow[w] = wlow;
             S.wd[w] = wd;
             S.wnd[w] = wnd;
             S.wlb[w] = wlb;
@@ -230,7 +243,10 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
                 bw = v;
         }
         int res = -1;
-        if (bw >= 0) {
+        double low = INFINITY;
+        for (int v = 0; v < NW; ++v) low = fmin(low, S.wlow[v]);
+        const int numeric = bw >= 0 ? (low < S.wd[bw]) : (low < INFINITY);
+        if (bw >= 0 && !numeric) {
             *r_out = S.wd[bw];
             x_out[0] = S.wx[bw][0];
             x_out[1] = S.wx[bw][1];
@@ -239,6 +255,7 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
             res = S.wk[bw];
         }
         __syncthreads();
+        if (numeric) return -2;
         if (res > 0) return res;
         if (isinf(bound)) break;
         bound = INFINITY;  // the witness bound was not beaten: search without it

@@ -30,11 +30,12 @@
 namespace sdfi {
 namespace geom {
 
-constexpr int KMAX = 64;             // working cap subset per wavefront
+constexpr int KMAX = 128;            // working cap subset per wavefront
 constexpr double TWO_PI = 6.283185307179586476925286766559;
 constexpr double ARC_EPS = 1e-12;    // angles within this of an arc end count as uncovered
 constexpr double NUDGE = 1e-7;       // witnesses move this far (rad) off the rim they sit on
 constexpr double COVER_EPS = 1e-13;  // cover margins v.u - c up to this count as uncovered (rounding)
+constexpr int64_t FALLBACK_MAX = 4096;  // exhaustive rim walks only for spheres with at most this many caps
 
 enum { ST_NONE = 0, ST_FOUND = 1, ST_NUMERIC = 2 };
 
@@ -57,6 +58,11 @@ struct Balls {
     double lq[3];
     double lb;
     const int64_t *idx;  // optional: the balls are rows idx[0..N) of p4 instead of [0, N)
+    // optional region of interest on the searched sphere, the cap {v : v.ru >= rc}
+    // (rs = sqrt(1 - rc^2)); caps that cannot meet it are ignored.  Exact for
+    // every question asked about points of the region.
+    int use_region;
+    double ru[3], rc, rs;
 };
 
 __device__ inline double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
@@ -89,6 +95,16 @@ __device__ inline int cap_of(const Balls &B, int64_t f, const double *o, double 
     cap.u[1] = v[1] / D;
     cap.u[2] = v[2] / D;
     cap.c = (r * r + D * D - R * R) / (2.0 * r * D);
+    if (B.use_region) {
+        // two caps of angular radii a_f, a_q meet iff the angle between their axes
+        // is below a_f + a_q: always when a_f + a_q >= pi (c_f <= -rc), otherwise
+        // iff u_f.ru > cos(a_f + a_q) = c_f rc - s_f rs
+        double cf = fmin(1.0, fmax(-1.0, cap.c));
+        if (cf > -B.rc + 1e-12) {
+            double sf = sqrt(fmax(0.0, 1.0 - cf * cf));
+            if (!(dot3(cap.u, B.ru) > cf * B.rc - sf * B.rs - 1e-12)) return 0;
+        }
+    }
     return 1;
 }
 
@@ -257,6 +273,19 @@ __device__ inline void wave_cover(const Balls &B, const double *o, double r, con
     *whole = wor(wh);
 }
 
+// number of caps on sphere (o, r), wave-reduced
+__device__ inline int64_t wave_count_caps(const Balls &B, const double *o, double r) {
+    const int lane = threadIdx.x & 63;
+    int64_t cnt = 0;
+    const int64_t n = ball_count(B);
+    for (int64_t f = lane; f < n; f += 64) {
+        Cap cp;
+        if (cap_of(B, f, o, r, cp) == 1) ++cnt;
+    }
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+    return cnt;
+}
+
 // Exact: does sphere (o, r) have a point no ball covers?  Writes one (nudged
 // off the rim it was found on) to x.  kp: this wave's LDS scratch (KMAX caps),
 // kid: their ball indices.  hint orders the search only.
@@ -307,16 +336,18 @@ __device__ inline int lazy_exist(const Balls &B, const double *o, double r, cons
     wave_sync_lds();
     for (int round = 0; round < 4 * KMAX; ++round) {
         // 1. uncovered gap midpoints w.r.t. the working subset, one rim per lane
-        int found = 0, numeric = 0;
+        // each lane walks rims lane and lane + 64 of the subset; keeps the first hit
+        int found = 0, numeric = 0, frim = -1;
         double tmid = 0.0;
         Rim R;
-        if (lane < k) {
-            make_rim(kp[lane], R);
+        for (int e = lane; e < k && !found; e += 64) {
+            make_rim(kp[e], R);
             double t, adv;
-            int st = rim_walk(R, kp, k, lane, 0.0, 1, &t, &adv);
+            int st = rim_walk(R, kp, k, e, 0.0, 1, &t, &adv);
             if (st == 1) {
                 found = 1;
-                tmid = t + 0.5 * gap_length(R, kp, k, lane, t);
+                frim = e;
+                tmid = t + 0.5 * gap_length(R, kp, k, e, t);
             } else if (st == 2) {
                 numeric = 1;
             }
@@ -327,20 +358,22 @@ __device__ inline int lazy_exist(const Balls &B, const double *o, double r, cons
         }
         // 2. verify candidates in lane order; collect the cap covering each
         int added = 0;
-        for (int cl = 0; cl < k; ++cl) {
+        for (int cl = 0; cl < 64; ++cl) {
             int f_cl = __shfl(found, cl, 64);
             if (!f_cl) continue;
+            int rim_cl = __shfl(frim, cl, 64);
             double v[3] = {0.0, 0.0, 0.0};
             if (lane == cl) rim_dir(R, tmid, v);
             v[0] = __shfl(v[0], cl, 64);
             v[1] = __shfl(v[1], cl, 64);
             v[2] = __shfl(v[2], cl, 64);
-            int64_t self = kid[cl];
+            int64_t self = kid[rim_cl];
             wave_cover(B, o, r, v, self, &mx, &arg, &whole);
             if (!(mx > COVER_EPS)) {
                 // verified; try to move it off the rim of `self`
-                double uv = dot3(kp[cl].u, v);
-                double tg[3] = {kp[cl].u[0] - uv * v[0], kp[cl].u[1] - uv * v[1], kp[cl].u[2] - uv * v[2]};
+                double uv = dot3(kp[rim_cl].u, v);
+                double tg[3] = {kp[rim_cl].u[0] - uv * v[0], kp[rim_cl].u[1] - uv * v[1],
+                                kp[rim_cl].u[2] - uv * v[2]};
                 double tn = sqrt(dot3(tg, tg));
                 if (tn > 0.0) {
                     double w[3] = {v[0] - NUDGE * tg[0] / tn, v[1] - NUDGE * tg[1] / tn, v[2] - NUDGE * tg[2] / tn};
@@ -378,6 +411,9 @@ __device__ inline int lazy_exist(const Balls &B, const double *o, double r, cons
         if (added == 0) break;  // subset full or no progress: fall back
     }
     // Fallback: walk every rim of every cap (lanes over rims), caps recomputed.
+    // Its cost grows with the cube of the cap count, so it is bounded: beyond
+    // FALLBACK_MAX caps the search reports a numeric failure instead.
+    if (wave_count_caps(B, o, r) > FALLBACK_MAX) return ST_NUMERIC;
     const int64_t n = ball_count(B);
     int64_t first = INT64_MAX;
     double fx[3] = {0.0, 0.0, 0.0};
@@ -441,18 +477,37 @@ __device__ inline int lazy_exist(const Balls &B, const double *o, double r, cons
 // Nearest point to q of the uncovered part of sphere (o, r) if nearer than
 // bound (strictly less or equal kept: ties are broken by the caller).
 // Returns 0 none, 1 radial foot point (T), 2 rim nearest point (D), 3 rim arc
-// end (U); writes distance and point.
-__device__ inline int lazy_nearest(const Balls &B, const double *o, double r, const double *q, double bound, Cap *kp,
+// end (U), -1 numeric failure; writes distance and point.
+__device__ inline int lazy_nearest(const Balls &B0, const double *o, double r, const double *q, double bound, Cap *kp,
                                    int64_t *kid, double *dist_out, double *x) {
     const int lane = threadIdx.x & 63;
     double g[3] = {q[0] - o[0], q[1] - o[1], q[2] - o[2]};
     double gn = sqrt(dot3(g, g));
+    // only points of the sphere within `bound` of q matter: the cap v.g/|g| >= rc
+    Balls B = B0;
+    B.use_region = 0;
+    if (bound < INFINITY && gn > 0.0) {
+        double rc = (r * r + gn * gn - bound * bound) / (2.0 * r * gn);
+        if (rc > 1.0) return 0;  // no point of the sphere is that close
+        if (rc > -1.0) {
+            B.use_region = 1;
+            B.ru[0] = g[0] / gn;
+            B.ru[1] = g[1] / gn;
+            B.ru[2] = g[2] / gn;
+            B.rc = rc;
+            B.rs = sqrt(fmax(0.0, 1.0 - rc * rc));
+        }
+    }
     double mx;
     int64_t arg;
     int whole;
     if (!(gn > 0.0)) {
         if (r > bound) return 0;
         int s = lazy_exist(B, o, r, nullptr, kp, kid, x);
+        if (s == ST_NUMERIC) {
+            *dist_out = r;
+            return -1;
+        }
         if (s != ST_FOUND) return 0;
         *dist_out = r;
         return 1;
@@ -473,12 +528,13 @@ __device__ inline int lazy_nearest(const Balls &B, const double *o, double r, co
         cap_of(B, arg, o, r, kp[0]);
     }
     wave_sync_lds();
+    double lowest = d0;  // every uncovered point is at least this far from q
     for (int round = 0; round < 8 * KMAX; ++round) {
         double cd = INFINITY, ct_ = 0.0;
-        int ckind = 0;
-        Rim R;
-        if (lane < k) {
-            make_rim(kp[lane], R);
+        int ckind = 0, crim = -1;
+        Rim R, Rb;
+        for (int e = lane; e < k; e += 64) {
+            make_rim(kp[e], R);
             // lower bound: distance from q to the rim circle
             double ug = dot3(R.u, g);
             double perp = sqrt(fmax(gn * gn - ug * ug, 0.0));
@@ -486,40 +542,47 @@ __device__ inline int lazy_nearest(const Balls &B, const double *o, double r, co
             double lbd = sqrt(fmax(r * r + gn * gn - 2.0 * r * vg, 0.0));
             if (lbd <= bound) {
                 double ts = atan2(dot3(R.e2, g), dot3(R.e1, g));
-                double tp, ap, tm, am;
-                int sp = rim_walk(R, kp, k, lane, ts, 1, &tp, &ap);
+                double tp, ap, tm, am, tt = 0.0;
+                int kind_e = 0;
+                int sp = rim_walk(R, kp, k, e, ts, 1, &tp, &ap);
                 if (sp == 1 && ap == 0.0) {
-                    ct_ = ts;
-                    ckind = 2;
+                    tt = ts;
+                    kind_e = 2;
                 } else if (sp == 1) {
-                    int sm = rim_walk(R, kp, k, lane, ts, -1, &tm, &am);
-                    ct_ = (sm == 1 && am < ap) ? tm : tp;
-                    ckind = 3;
+                    int sm = rim_walk(R, kp, k, e, ts, -1, &tm, &am);
+                    tt = (sm == 1 && am < ap) ? tm : tp;
+                    kind_e = 3;
                 }
-                if (ckind) {
+                if (kind_e) {
                     double v[3];
-                    rim_dir(R, ct_, v);
+                    rim_dir(R, tt, v);
                     double y[3] = {o[0] + r * v[0], o[1] + r * v[1], o[2] + r * v[2]};
-                    cd = dist3(y, q);
-                    if (cd > bound) {
-                        ckind = 0;
-                        cd = INFINITY;
+                    double de = dist3(y, q);
+                    if (de <= bound && de < cd) {
+                        cd = de;
+                        ct_ = tt;
+                        ckind = kind_e;
+                        crim = e;
+                        Rb = R;
                     }
                 }
             }
         }
         double best = wmin(cd);
         if (best == INFINITY) return 0;
+        lowest = fmax(lowest, best);  // the subset-nearest distance never exceeds the true one
         // lowest lane with the best distance
-        int64_t cand = (cd == best && ckind) ? lane : INT64_MAX;
-        int src = (int)wmin_i64(cand);
+        int64_t cand = (cd == best && ckind) ? ((int64_t)crim << 8) + lane : INT64_MAX;
+        int64_t pick = wmin_i64(cand);
+        int src = (int)(pick & 255);
+        int srim = (int)(pick >> 8);
         double v[3] = {0.0, 0.0, 0.0};
-        if (lane == src) rim_dir(R, ct_, v);
+        if (lane == src) rim_dir(Rb, ct_, v);
         v[0] = __shfl(v[0], src, 64);
         v[1] = __shfl(v[1], src, 64);
         v[2] = __shfl(v[2], src, 64);
         int kind = __shfl(ckind, src, 64);
-        wave_cover(B, o, r, v, kid[src], &mx, &arg, &whole);
+        wave_cover(B, o, r, v, kid[srim], &mx, &arg, &whole);
         if (!(mx > COVER_EPS)) {
             for (int j = 0; j < 3; ++j) x[j] = o[j] + r * v[j];
             *dist_out = best;
@@ -535,15 +598,29 @@ __device__ inline int lazy_nearest(const Balls &B, const double *o, double r, co
         wave_sync_lds();
         ++k;
     }
-    // Fallback: every rim against every cap.
+    // Fallback: every rim against every cap (bounded as in lazy_exist).  When
+    // capped, return -1 with the last subset-nearest distance, a lower bound.
+    if (wave_count_caps(B, o, r) > FALLBACK_MAX) {
+        *dist_out = lowest;
+        return -1;
+    }
     const int64_t n = ball_count(B);
     double bd = INFINITY, bx[3] = {0.0, 0.0, 0.0};
     int bkind = 0;
-    for (int64_t e = lane; e < n; e += 64) {
-        Cap ce;
-        if (cap_of(B, e, o, r, ce) != 1) continue;
-        Rim R;
+    double wbest = bound;  // wave-wide best so far: rims farther than it are skipped
+    for (int64_t e0 = 0; e0 < n; e0 += 64) {
+      const int64_t e = e0 + lane;
+      Cap ce;
+      Rim R;
+      bool live = e < n && cap_of(B, e, o, r, ce) == 1;
+      if (live) {
         make_rim(ce, R);
+        double ug = dot3(R.u, g);
+        double perp = sqrt(fmax(gn * gn - ug * ug, 0.0));
+        double lbd = sqrt(fmax(r * r + gn * gn - 2.0 * r * (R.c * ug + R.rho * perp), 0.0));
+        live = lbd <= wbest * (1.0 + 1e-12) + 1e-15;  // a rim farther than the best cannot win
+      }
+      if (live) {
         double ts = atan2(dot3(R.e2, g), dot3(R.e1, g));
         double tt[2];
         int kinds[2] = {0, 0};
@@ -592,6 +669,8 @@ __device__ inline int lazy_nearest(const Balls &B, const double *o, double r, co
                 bx[2] = y[2];
             }
         }
+      }
+      wbest = fmin(wbest, wmin(bd));
     }
     double best = wmin(bd);
     if (!(best <= bound)) return 0;

@@ -111,6 +111,7 @@ __device__ void revalidate(const GInst &I, int64_t N, const double *q, double s,
         B.tol = tol;
         B.lb = INFINITY;
         B.idx = nullptr;
+        B.use_region = 0;
         for (int64_t guard = 0; guard <= nthr; ++guard) {
             int t = 0;
             if (ln == 0) t = atomicAdd(&SH.counter, 1);
@@ -238,6 +239,7 @@ __global__ __launch_bounds__(GBS) void greedy_kernel(const GInst *insts, double 
                             B.skip = -1;
                             B.lb = INFINITY;
                             B.idx = nullptr;
+        B.use_region = 0;
                             double x[3];
                             int st = geom::lazy_exist(B, q, r, cw[e], SH.kp[0], SH.kid[0], x);
                             if (ln == 0) {
@@ -285,6 +287,7 @@ __global__ __launch_bounds__(GBS) void greedy_kernel(const GInst *insts, double 
                         int64_t sph;
                         int kk = blk::rmin_block<NW>(q, sigma, I.CP, I.CW, N, tol, tie, I.list, SH.kp, SH.kid, SH.S,
                                                      &rr, x, &sph);
+                        if (kk == -2 && tid == 0) atomicAdd(&I.counts[C_NUMERIC], 1ull);
                         if (kk > 0) {
                             val = sigma * rr;
                             kindv = kk == 1 ? SDFI_KIND_RMIN_T : (kk == 2 ? SDFI_KIND_RMIN_D : SDFI_KIND_RMIN_U);
@@ -393,6 +396,7 @@ __global__ __launch_bounds__(256) void witness_kernel(const double *p4, int64_t 
         B.skip = i;
         B.lb = INFINITY;
         B.idx = nullptr;
+        B.use_region = 0;
         double x[3];
         int st = geom::lazy_exist(B, pi, fabs(pi[3]), be != INT64_MAX ? p4 + 4 * be : nullptr, kp[w], kid[w], x);
         if (ln == 0) {
@@ -446,7 +450,7 @@ size_t greedy_ws(int64_t n, int64_t m, const sdfi_options &o) {
     Carver c(nullptr, 0, true);
     carve_greedy(c, n, m, 1);
     Carver c2(nullptr, 0, true);
-    size_t ord = o.grid > 0 ? order_ws(n, m, o) : 0;
+    size_t ord = order_ws(n, m, o);
     size_t cert = (o.flags & SDFI_OPT_CERTIFY) ? certify_ws(n + m, o) + 4 * (n + m) * 8 + 3 * (n + m) * 8 + 1024 : 0;
     return c.used + std::max(ord, cert) + 1024;
 }
@@ -551,7 +555,9 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
         g.active = active + qoff[i];
         g.kind = kind + qoff[i];
         g.witness = witness + 3 * qoff[i];
-        g.sample_witness = sample_witness ? sample_witness + 3 * soff[i] : nullptr;
+        // final sample witnesses go to the caller, else back into the workspace copy
+        // (the certificate below reads them from there)
+        g.sample_witness = sample_witness ? sample_witness + 3 * soff[i] : b.win + 3 * soff[i];
         g.order_out = order_out + qoff[i];
         g.CP = b.CP + 4 * cpos;
         g.CW = b.CW + 3 * cpos;
@@ -588,7 +594,7 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
             report->n_infeasible += cc[C_INFEAS];
             report->n_unresolved += cc[C_UNRES];
             report->n_exact_searches += cc[C_SEARCH];
-            report->n_fp64_rechecks += cc[C_NUMERIC];
+            report->n_search_capped += cc[C_NUMERIC];
         }
         report->pairs_evaluated = pairs;
         report->ms_phase[0] = t2 - t1;

@@ -103,8 +103,11 @@ std::vector<int64_t> flood(const std::vector<int> &cnt, int res) {
 }  // namespace
 
 size_t order_ws(int64_t n, int64_t m, const sdfi_options &o) {
+    // (2N)^3 cell counts; without a grid (batched instances) 8 n covers any
+    // instance of at most n samples
     int64_t fine = (int64_t)2 * o.grid;
-    return sizeof(int) * (size_t)std::max<int64_t>(fine * fine * fine, 1) + 4096;
+    int64_t cells = o.grid > 0 ? fine * fine * fine : 8 * n;
+    return sizeof(int) * (size_t)std::max<int64_t>(cells, 1) + 4096;
 }
 
 sdfi_status run_order(const double *samples, int64_t n, const double *queries, int64_t m, int64_t *order_out,

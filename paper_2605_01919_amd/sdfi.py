@@ -41,7 +41,8 @@ class Report(ctypes.Structure):
                 ("n_infeasible", ctypes.c_int64), ("n_unresolved", ctypes.c_int64),
                 ("n_fp64_rechecks", ctypes.c_int64), ("n_exact_searches", ctypes.c_int64),
                 ("n_violations_pairwise", ctypes.c_int64), ("n_violations_witness", ctypes.c_int64),
-                ("n_removed", ctypes.c_int64), ("ms_phase", ctypes.c_double * 8)]
+                ("n_removed", ctypes.c_int64), ("n_search_capped", ctypes.c_int64),
+                ("ms_phase", ctypes.c_double * 8)]
 
     def as_dict(self):
         d = {name: getattr(self, name) for name, _ in self._fields_ if name != "ms_phase"}

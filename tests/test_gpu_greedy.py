@@ -119,3 +119,66 @@ def test_input_check_rejects_covered_sample():
     Q = np.array([[0.5, 0.5, 0.5]])
     with pytest.raises(sdfi.SdfiError, match="status 4"):
         sdfi.greedy(dev(np.c_[P, S]), dev(Q), order=dev(np.array([0]), torch.int64), input_check=True)
+
+
+def test_batched_equals_plain():
+    # uneven instances in one launch give bit-identical results to separate calls
+    inst = configs.batch(6, grids=(4, 5, 6))
+    tens = [(dev(np.c_[x.points, x.values]), dev(x.queries), x.grid) for x in inst]
+    print("batched", [x.grid for x in inst], flush=True)
+    b = sdfi.greedy_batched(tens, certify=True)
+    rep = b["report"]
+    if rep["n_violations_witness"] or rep["n_violations_pairwise"]:
+        print("report", rep, flush=True)
+        so, qo = b["sample_offsets"], b["query_offsets"]
+        for i, x in enumerate(inst):
+            sl = slice(qo[i], qo[i + 1])
+            vals = b["values"][sl].cpu().numpy()
+            kinds = b["kind"][sl].cpu().numpy()
+            order = b["order"][sl].cpu().numpy()
+            p = sdfi.greedy(tens[i][0], tens[i][1], grid=x.grid, sample_witness=True)
+            P = np.vstack([x.points, x.queries])
+            S = np.concatenate([x.values, vals])
+            Wt = np.vstack([p["sample_witness"].cpu().numpy(), b["witness"][sl].cpu().numpy()])
+            R = np.abs(S)
+            kall = np.concatenate([np.zeros(x.n, int), kinds])
+            step = np.full(len(S), -1)
+            step[x.n + order] = np.arange(len(order))
+            shown = 0
+            for a in range(len(S)):
+                dw = dist(P, Wt[a])
+                cov = dw < R - TOL - 1e-9
+                cov[a] = False
+                off = abs(dist(Wt[a], P[a]) - R[a]) > TOL
+                if (cov.any() or off) and shown < 4:
+                    shown += 1
+                    c = int(np.nonzero(cov)[0][0]) if cov.any() else -1
+                    print("inst", i, "witness of", a, "kind", kall[a], "step", step[a], "off", off, "covered by", c,
+                          "kind", kall[c], "step", step[c], "margin", (R[c] - TOL - dw[c]) if c >= 0 else 0, flush=True)
+    assert rep["n_violations_pairwise"] == 0 and rep["n_violations_witness"] == 0
+    qo = b["query_offsets"]
+    for i, (s, q, g) in enumerate(tens):
+        p = sdfi.greedy(s, q, grid=g)
+        sl = slice(qo[i], qo[i + 1])
+        assert torch.equal(b["values"][sl], p["values"])
+        assert torch.equal(b["kind"][sl], p["kind"])
+        if not torch.equal(b["active"][sl], p["active"]):
+            bad = torch.nonzero(b["active"][sl] != p["active"]).flatten()[:5].tolist()
+            print("active mismatch", i, [(j, int(p["kind"][j]), float(p["values"][j]), int(b["active"][sl][j]),
+                                          int(p["active"][j])) for j in bad], flush=True)
+        assert torch.equal(b["active"][sl], p["active"])
+        assert torch.equal(b["order"][sl], p["order"])
+
+
+def test_batched_instance_matches_oracle():
+    # a box on a coarse grid; a value depends only on earlier ones, so the
+    # first 400 steps are compared (the oracle's later steps take minutes here)
+    x = configs.batch_instance(2, grids=(5,))
+    b = sdfi.greedy_batched([(dev(np.c_[x.points, x.values]), dev(x.queries), x.grid)])
+    print("batched instance done on the GPU", flush=True)
+    W, ok = OG.input_witnesses(x.points, x.values)
+    order, _, _ = OO.refinement_order(x.points, x.values, x.grid)
+    np.testing.assert_array_equal(b["order"].cpu().numpy(), order)
+    r = OG.greedy_interpolate(x.points, x.values, x.queries, order, W, stop=400, progress=100)
+    head = order[:400]
+    np.testing.assert_allclose(b["values"].cpu().numpy()[head], r.values[head], rtol=0, atol=1e-5)
