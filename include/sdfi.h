@@ -209,7 +209,9 @@ sdfi_status sdfi_sample_witnesses(const double *samples, int64_t n, double *witn
  *   query sphere, as last updated); sample_witness: n x 3 or NULL.
  * m < 2^31 and n + m < 2^31.  Synchronises the stream.
  * report (host, may be NULL): counts; ms_phase[0] order, [1] witnesses,
- * [2] greedy, [3] certificate. */
+ * [2] greedy, [3] certificate; [4..7] device time of the greedy steps spent
+ * in the bound scans, the candidate checks, the minimum valid radius and the
+ * bookkeeping (summed over instances, device wall clock). */
 sdfi_status sdfi_greedy_interpolate(const double *samples, int64_t n, const double *queries, int64_t m,
                                     const int64_t *order_in, double *values, int64_t *order_out,
                                     int64_t *active, uint8_t *kind, double *witness, double *sample_witness,

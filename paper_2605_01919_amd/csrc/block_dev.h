@@ -147,6 +147,43 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
     }
     deepest = bmin_i64(deepest, S);
     double bound = isinf(wbest) ? INFINITY : wbest * (1.0 + 1e-12) + 1e-15;
+    // A second upper bound: the exit of the ray from q away from the deepest
+    // centre.  At each point of the ray, jump to the farthest exit among the
+    // balls (shrunk by tie) holding it; the first point no ball holds is off
+    // the union, so the contour is no farther from q than that point.
+    {
+        const double *pd = p4 + 4 * deepest;
+        double dir[3] = {q[0] - pd[0], q[1] - pd[1], q[2] - pd[2]};
+        double dn = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+        if (!(dn > 0.0)) {
+            dir[0] = 1.0;
+            dir[1] = 0.0;
+            dir[2] = 0.0;
+            dn = 1.0;
+        }
+        for (int j = 0; j < 3; ++j) dir[j] /= dn;
+        double t = 0.0;
+        for (int it = 0; it < 64; ++it) {
+            const double x[3] = {q[0] + t * dir[0], q[1] + t * dir[1], q[2] + t * dir[2]};
+            double step = 0.0;
+            for (int64_t c = tid; c < N; c += BS) {
+                const double *p = p4 + 4 * c;
+                if (sign_class(p[3], tie) != sigma) continue;
+                const double R = fabs(p[3]) - tie;
+                const double w[3] = {x[0] - p[0], x[1] - p[1], x[2] - p[2]};
+                const double cc = w[0] * w[0] + w[1] * w[1] + w[2] * w[2] - R * R;
+                if (!(R > 0.0) || !(cc < 0.0)) continue;
+                const double b = dir[0] * w[0] + dir[1] * w[1] + dir[2] * w[2];
+                step = fmax(step, -b + sqrt(b * b - cc));
+            }
+            step = bmax(step, S);
+            if (!(step > 0.0)) {
+                bound = fmin(bound, t * (1.0 + 1e-12) + 1e-12);
+                break;
+            }
+            t += step + 1e-12;  // strictly past the exit of the ball left behind
+        }
+    }
     int64_t *lset = list + (N + 1);
     for (int pass = 0; pass < 2; ++pass) {
         // candidate spheres: sigma spheres passing within `bound` of q (deepest first)

@@ -7,10 +7,15 @@
 // The rim of cap e is v(t) = c_e u_e + rho_e (cos t e1 + sin t e2); cap f
 // covers the open arc A cos t + B sin t > K of that rim with
 //   A = rho_e e1.u_f, B = rho_e e2.u_f, K = c_f - c_e u_e.u_f.
+// Rim points are kept as unit vectors P = (cos t, sin t): an arc is its
+// centre direction C = (A, B)/|(A, B)| and its half-width beta, cos beta =
+// K/|(A, B)|, so its ends are C rotated by -beta and +beta and no angle is
+// ever formed; advances along the rim are ordered by a monotone stand-in for
+// the angle (no trigonometric function is evaluated anywhere).
 //
-// Rim walk.  Starting at an angle, if some arcs cover it, jump to the
-// farthest end among them; stop at the first angle no arc covers or after a
-// full turn (rim covered).  Each arc is jumped over at most once per turn.
+// Rim walk.  Starting at a point, if some arcs cover it, jump to the
+// farthest end among them; stop at the first point no arc covers or when the
+// start is passed (rim covered).  Each arc is jumped over at most once per turn.
 //
 // Lazy search.  A sphere with caps K has an uncovered point iff it has one
 // w.r.t. every subset; the search keeps a working subset K' (<= KMAX caps in
@@ -31,8 +36,7 @@ namespace sdfi {
 namespace geom {
 
 constexpr int KMAX = 128;            // working cap subset per wavefront
-constexpr double TWO_PI = 6.283185307179586476925286766559;
-constexpr double ARC_EPS = 1e-12;    // angles within this of an arc end count as uncovered
+constexpr double ARC_EPS = 1e-12;    // points with C.P - cos beta up to this count as uncovered
 constexpr double NUDGE = 1e-7;       // witnesses move this far (rad) off the rim they sit on
 constexpr double COVER_EPS = 1e-13;  // cover margins v.u - c up to this count as uncovered (rounding)
 constexpr int64_t FALLBACK_MAX = 4096;  // exhaustive rim walks only for spheres with at most this many caps
@@ -140,78 +144,145 @@ __device__ inline void make_rim(const Cap &cp, Rim &R) {
     basis(cp.u, R.e1, R.e2);
 }
 
-__device__ inline void rim_dir(const Rim &R, double t, double *v) {
-    double ct = cos(t), st = sin(t);
-    for (int j = 0; j < 3; ++j) v[j] = R.c * R.u[j] + R.rho * (ct * R.e1[j] + st * R.e2[j]);
+// point of the rim at P = (cos t, sin t)
+__device__ inline void rim_dir(const Rim &R, double px, double py, double *v) {
+    for (int j = 0; j < 3; ++j) v[j] = R.c * R.u[j] + R.rho * (px * R.e1[j] + py * R.e2[j]);
 }
 
-// arc of cap f on rim R: returns 0 none, 1 arc (phi, beta), 2 whole rim
-__device__ inline int arc_of(const Rim &R, const Cap &f, double &A, double &Bc, double &K, double &amp) {
-    A = R.rho * dot3(R.e1, f.u);
-    Bc = R.rho * dot3(R.e2, f.u);
-    K = f.c - R.c * dot3(R.u, f.u);
-    amp = hypot(A, Bc);
+struct Arc {
+    double cx, cy;  // centre direction
+    double k, s;    // cos and sin of the half-width
+};
+
+// arc of cap f on rim R: returns 0 none, 1 arc, 2 whole rim
+__device__ inline int arc_of(const Rim &R, const Cap &f, Arc &a) {
+    const double A = R.rho * dot3(R.e1, f.u), Bc = R.rho * dot3(R.e2, f.u);
+    const double K = f.c - R.c * dot3(R.u, f.u);
+    const double amp = sqrt(A * A + Bc * Bc);
     if (K < -amp) return 2;
     if (!(amp > K)) return 0;
+    a.cx = A / amp;
+    a.cy = Bc / amp;
+    a.k = fmin(1.0, fmax(-1.0, K / amp));
+    a.s = sqrt(fmax(0.0, 1.0 - a.k * a.k));
     return 1;
 }
 
-__device__ inline double wrap_pos(double d) {
-    // into (0, 2 pi]
-    d = fmod(d, TWO_PI);
-    if (d <= 0.0) d += TWO_PI;
-    return d;
+__device__ inline bool arc_covers(const Arc &a, double px, double py) { return a.cx * px + a.cy * py - a.k > ARC_EPS; }
+
+// dir > 0: the end met walking forward (C rotated by +beta); dir < 0: the start
+__device__ inline void arc_end(const Arc &a, int dir, double &ex, double &ey) {
+    const double s = dir > 0 ? a.s : -a.s;
+    ex = a.cx * a.k - a.cy * s;
+    ey = a.cy * a.k + a.cx * s;
 }
 
-// Walk rim R over caps kp[0..k) (skipping index `self`) from angle t0 in
+// increasing function of the forward angle in [0, 2 pi) from P to E
+__device__ inline double pseudo_angle(double px, double py, double ex, double ey) {
+    const double d = px * ex + py * ey, cr = px * ey - py * ex;
+    return cr >= 0.0 ? 1.0 - d : 3.0 + d;
+}
+
+// Caps of a rim walk: the wave's working subset, or every cap of the sphere.
+struct SubsetCaps {
+    const Cap *kp;
+    int k;
+    __device__ int64_t count() const { return k; }
+    __device__ bool get(int64_t f, Cap &c) const {
+        c = kp[f];
+        return true;
+    }
+};
+struct AllCaps {
+    const Balls *B;
+    const double *o;
+    double r;
+    __device__ int64_t count() const { return ball_count(*B); }
+    __device__ bool get(int64_t f, Cap &c) const { return cap_of(*B, f, o, r, c) == 1; }
+};
+
+// Walk rim R over the caps of `src` (skipping index `self`) from P0 in
 // direction dir (+1 forward to arc ends, -1 backward to arc starts).
-// Returns 1 with *t_out = first uncovered angle and *adv its distance from t0,
-// 0 if the rim is covered, 2 if the step cap was hit.
-__device__ inline int rim_walk(const Rim &R, const Cap *kp, int k, int self, double t0, int dir, double *t_out,
-                               double *adv_out) {
-    double t = t0, adv = 0.0;
-    for (int it = 0; it <= k + 4; ++it) {
-        double ct = cos(t), st = sin(t);
-        double step = 0.0;
+// Returns 1 with the first uncovered point and whether the walk moved, 0 if
+// the rim is covered, 2 if the step cap was hit.
+template <class Src>
+__device__ inline int rim_walk(const Rim &R, const Src &src, int64_t self, double p0x, double p0y, int dir,
+                               int64_t max_it, double *px_out, double *py_out, int *moved) {
+    double px = p0x, py = p0y;
+    int mv = 0;
+    const int64_t k = src.count();
+    for (int64_t it = 0; it <= max_it; ++it) {
         bool cov = false;
-        for (int f = 0; f < k; ++f) {
+        double best = -1.0, bx = px, by = py;
+        for (int64_t f = 0; f < k; ++f) {
             if (f == self) continue;
-            double A, Bc, K, amp;
-            int a = arc_of(R, kp[f], A, Bc, K, amp);
-            if (a == 2) return 0;
-            if (a == 0) continue;
-            double val = A * ct + Bc * st - K;
-            if (!(val > ARC_EPS * amp)) continue;
+            Cap cf;
+            if (!src.get(f, cf)) continue;
+            Arc a;
+            const int st = arc_of(R, cf, a);
+            if (st == 2) return 0;
+            if (st == 0 || !arc_covers(a, px, py)) continue;
             cov = true;
-            double phi = atan2(Bc, A);
-            double beta = acos(fmin(1.0, fmax(-1.0, K / amp)));
-            double d = dir > 0 ? wrap_pos(phi + beta - t) : wrap_pos(t - (phi - beta));
-            step = fmax(step, d);
+            double ex, ey;
+            arc_end(a, dir, ex, ey);
+            const double pa = dir > 0 ? pseudo_angle(px, py, ex, ey) : pseudo_angle(ex, ey, px, py);
+            if (pa > best) {
+                best = pa;
+                bx = ex;
+                by = ey;
+            }
         }
         if (!cov) {
-            *t_out = t;
-            *adv_out = adv;
+            *px_out = px;
+            *py_out = py;
+            *moved = mv;
             return 1;
         }
-        adv += step;
-        if (adv >= TWO_PI) return 0;
-        t += dir > 0 ? step : -step;
+        // a full turn: the start lies in the stretch (P, E] about to be jumped
+        if (mv) {
+            const double ps = dir > 0 ? pseudo_angle(px, py, p0x, p0y) : pseudo_angle(p0x, p0y, px, py);
+            if (ps <= best) return 0;
+        }
+        const double nn = sqrt(bx * bx + by * by);
+        px = bx / nn;
+        py = by / nn;
+        mv = 1;
     }
     return 2;
 }
 
-// angular length of the uncovered gap that starts at t (forward), <= 2 pi
-__device__ inline double gap_length(const Rim &R, const Cap *kp, int k, int self, double t) {
-    double best = TWO_PI;
+// Midpoint of the uncovered stretch that starts at P (forward) among caps
+// kp[0..k) other than `self`.
+__device__ inline void gap_mid(const Rim &R, const Cap *kp, int k, int self, double px, double py, double *mx,
+                               double *my) {
+    double best = 5.0, sx = 0.0, sy = 0.0;
     for (int f = 0; f < k; ++f) {
         if (f == self) continue;
-        double A, Bc, K, amp;
-        if (arc_of(R, kp[f], A, Bc, K, amp) != 1) continue;
-        double phi = atan2(Bc, A);
-        double beta = acos(fmin(1.0, fmax(-1.0, K / amp)));
-        best = fmin(best, wrap_pos(phi - beta - t));
+        Arc a;
+        if (arc_of(R, kp[f], a) != 1) continue;
+        double ex, ey;
+        arc_end(a, -1, ex, ey);
+        const double pa = pseudo_angle(px, py, ex, ey);
+        if (pa < best) {
+            best = pa;
+            sx = ex;
+            sy = ey;
+        }
     }
-    return best;
+    if (best > 4.0) {  // no arc: the whole rim is free, take the antipode
+        *mx = -px;
+        *my = -py;
+        return;
+    }
+    const double hx = px + sx, hy = py + sy, hn = sqrt(hx * hx + hy * hy);
+    if (hn < 1e-8) {  // half a turn: a quarter turn forward
+        *mx = -py;
+        *my = px;
+        return;
+    }
+    const double sg = best <= 2.0 ? 1.0 : -1.0;
+    *mx = sg * hx / hn;
+    *my = sg * hy / hn;
 }
 
 // ---- wave-level helpers (all 64 lanes call them together) ----
@@ -244,26 +315,61 @@ __device__ inline int wor(int v) {
 // Largest cover margin v.u_f - c_f over all caps of the sphere (ball `excl`
 // left out) and the smallest ball index attaining it; also reports a ball
 // holding the whole sphere.  margin > 0 means v is covered.
+//
+// The cap margin equals (R^2 - |x - p|^2) / (2 r D) for x = o + r v, so balls
+// with R^2 - |x - p|^2 <= -PRE_EPS neither cover x nor hold the sphere and are
+// skipped before the cap is formed (PRE_EPS is far above the rounding of
+// either expression, so no ball that the cap form would count is skipped).
+// Balls are read U rows per lane at a time so that their loads overlap.
+constexpr double PRE_EPS = 1e-12;
+
 __device__ inline void wave_cover(const Balls &B, const double *o, double r, const double *v, int64_t excl,
-                                  double *mx, int64_t *arg, int *whole) {
+                                  double *mx, int64_t *arg, int *whole, int *holds_region = nullptr) {
+    constexpr int U = 4;
     const int lane = threadIdx.x & 63;
+    const double x[3] = {o[0] + r * v[0], o[1] + r * v[1], o[2] + r * v[2]};
     double best = -INFINITY;
     int64_t bi = INT64_MAX;
-    int wh = 0;
+    int wh = 0, hr = 0;
+    const bool region = holds_region && B.use_region;
     const int64_t n = ball_count(B);
-    for (int64_t f = lane; f < n; f += 64) {
-        if (f == excl) continue;
-        Cap cp;
-        int s = cap_of(B, f, o, r, cp);
-        if (s == 2) {
-            wh = 1;
-            continue;
+    for (int64_t f0 = 0; f0 < n; f0 += 64 * U) {
+        double px[U], py[U], pz[U], ps[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t f = f0 + 64 * u + lane;
+            const double *p = ball_ptr(B, f < n ? f : n - 1);
+            px[u] = p[0];
+            py[u] = p[1];
+            pz[u] = p[2];
+            ps[u] = p[3];
         }
-        if (s == 0) continue;
-        double m = dot3(v, cp.u) - cp.c;
-        if (m > best) {
-            best = m;
-            bi = f;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t f = f0 + 64 * u + lane;
+            const double R = fabs(ps[u]) - B.tol;
+            const double dx = x[0] - px[u], dy = x[1] - py[u], dz = x[2] - pz[u];
+            const double pre = R * R - (dx * dx + dy * dy + dz * dz);
+            if (f >= n || f == excl || !(R > 0.0) || !(pre > -PRE_EPS)) continue;
+            Cap cp;
+            int s = cap_of(B, f, o, r, cp);
+            if (s == 2) {
+                wh = 1;
+                continue;
+            }
+            if (s == 0) continue;
+            double m = dot3(v, cp.u) - cp.c;
+            if (m > best) {
+                best = m;
+                bi = f;
+            }
+            // the region cap (axis ru, angular radius a) lies inside this open
+            // cap (axis u, angular radius b > a) iff angle(ru, u) < b - a, i.e.
+            // ru.u > cos(b - a) = c rc + sin(b) rs; kept with a margin
+            if (region && cp.c < B.rc - 1e-12) {
+                const double sb = sqrt(fmax(0.0, 1.0 - cp.c * cp.c));
+                if (dot3(B.ru, cp.u) > cp.c * B.rc + sb * B.rs + 1e-12) hr = 1;
+            }
         }
     }
     double g = wmax(best);
@@ -271,6 +377,7 @@ __device__ inline void wave_cover(const Balls &B, const double *o, double r, con
     *mx = g;
     *arg = wmin_i64(cand);
     *whole = wor(wh);
+    if (holds_region) *holds_region = wor(hr);
 }
 
 // number of caps on sphere (o, r), wave-reduced
@@ -335,19 +442,21 @@ __device__ inline int lazy_exist(const Balls &B, const double *o, double r, cons
     k = 1;
     wave_sync_lds();
     for (int round = 0; round < 4 * KMAX; ++round) {
-        // 1. uncovered gap midpoints w.r.t. the working subset, one rim per lane
-        // each lane walks rims lane and lane + 64 of the subset; keeps the first hit
+        // 1. uncovered gap midpoints w.r.t. the working subset: each lane walks
+        //    rims lane and lane + 64 of the subset and keeps the first hit
+        const SubsetCaps sub{kp, k};
         int found = 0, numeric = 0, frim = -1;
-        double tmid = 0.0;
+        double mxp = 0.0, myp = 0.0;
         Rim R;
         for (int e = lane; e < k && !found; e += 64) {
             make_rim(kp[e], R);
-            double t, adv;
-            int st = rim_walk(R, kp, k, e, 0.0, 1, &t, &adv);
+            double px, py;
+            int mv;
+            const int st = rim_walk(R, sub, e, 1.0, 0.0, 1, k + 4, &px, &py, &mv);
             if (st == 1) {
                 found = 1;
                 frim = e;
-                tmid = t + 0.5 * gap_length(R, kp, k, e, t);
+                gap_mid(R, kp, k, e, px, py, &mxp, &myp);
             } else if (st == 2) {
                 numeric = 1;
             }
@@ -359,25 +468,25 @@ __device__ inline int lazy_exist(const Balls &B, const double *o, double r, cons
         // 2. verify candidates in lane order; collect the cap covering each
         int added = 0;
         for (int cl = 0; cl < 64; ++cl) {
-            int f_cl = __shfl(found, cl, 64);
+            const int f_cl = __shfl(found, cl, 64);
             if (!f_cl) continue;
-            int rim_cl = __shfl(frim, cl, 64);
+            const int rim_cl = __shfl(frim, cl, 64);
             double v[3] = {0.0, 0.0, 0.0};
-            if (lane == cl) rim_dir(R, tmid, v);
+            if (lane == cl) rim_dir(R, mxp, myp, v);
             v[0] = __shfl(v[0], cl, 64);
             v[1] = __shfl(v[1], cl, 64);
             v[2] = __shfl(v[2], cl, 64);
-            int64_t self = kid[rim_cl];
+            const int64_t self = kid[rim_cl];
             wave_cover(B, o, r, v, self, &mx, &arg, &whole);
             if (!(mx > COVER_EPS)) {
                 // verified; try to move it off the rim of `self`
-                double uv = dot3(kp[rim_cl].u, v);
-                double tg[3] = {kp[rim_cl].u[0] - uv * v[0], kp[rim_cl].u[1] - uv * v[1],
-                                kp[rim_cl].u[2] - uv * v[2]};
-                double tn = sqrt(dot3(tg, tg));
+                const double uv = dot3(kp[rim_cl].u, v);
+                const double tg[3] = {kp[rim_cl].u[0] - uv * v[0], kp[rim_cl].u[1] - uv * v[1],
+                                      kp[rim_cl].u[2] - uv * v[2]};
+                const double tn = sqrt(dot3(tg, tg));
                 if (tn > 0.0) {
                     double w[3] = {v[0] - NUDGE * tg[0] / tn, v[1] - NUDGE * tg[1] / tn, v[2] - NUDGE * tg[2] / tn};
-                    double wn = sqrt(dot3(w, w));
+                    const double wn = sqrt(dot3(w, w));
                     w[0] /= wn;
                     w[1] /= wn;
                     w[2] /= wn;
@@ -414,59 +523,28 @@ __device__ inline int lazy_exist(const Balls &B, const double *o, double r, cons
     // Its cost grows with the cube of the cap count, so it is bounded: beyond
     // FALLBACK_MAX caps the search reports a numeric failure instead.
     if (wave_count_caps(B, o, r) > FALLBACK_MAX) return ST_NUMERIC;
+    const AllCaps all{&B, o, r};
     const int64_t n = ball_count(B);
-    int64_t first = INT64_MAX;
-    double fx[3] = {0.0, 0.0, 0.0};
     for (int64_t e0 = 0; e0 < n; e0 += 64) {
-        int64_t e = e0 + lane;
-        if (e < n) {
-            Cap ce;
-            if (cap_of(B, e, o, r, ce) == 1) {
-                Rim R;
-                make_rim(ce, R);
-                // walk over all caps f != e, streamed in chunks of KMAX through registers
-                double t = 0.0, adv = 0.0;
-                int ok = 0;
-                for (int64_t it = 0; it < n + 8; ++it) {
-                    double ct = cos(t), st = sin(t), step = 0.0;
-                    bool cov = false, whole_rim = false;
-                    for (int64_t f = 0; f < n; ++f) {
-                        if (f == e) continue;
-                        Cap cf;
-                        int s = cap_of(B, f, o, r, cf);
-                        if (s != 1) continue;
-                        double A, Bc, K, amp;
-                        int a = arc_of(R, cf, A, Bc, K, amp);
-                        if (a == 2) {
-                            whole_rim = true;
-                            break;
-                        }
-                        if (a == 0) continue;
-                        if (!(A * ct + Bc * st - K > ARC_EPS * amp)) continue;
-                        cov = true;
-                        double phi = atan2(Bc, A), beta = acos(fmin(1.0, fmax(-1.0, K / amp)));
-                        step = fmax(step, wrap_pos(phi + beta - t));
-                    }
-                    if (whole_rim) break;
-                    if (!cov) {
-                        ok = 1;
-                        break;
-                    }
-                    adv += step;
-                    if (adv >= TWO_PI) break;
-                    t += step;
-                }
-                if (ok && e < first) {
-                    first = e;
-                    double v[3];
-                    rim_dir(R, t, v);
-                    for (int j = 0; j < 3; ++j) fx[j] = o[j] + r * v[j];
-                }
+        const int64_t e = e0 + lane;
+        int64_t first = INT64_MAX;
+        double fx[3] = {0.0, 0.0, 0.0};
+        Cap ce;
+        if (e < n && cap_of(B, e, o, r, ce) == 1) {
+            Rim R;
+            make_rim(ce, R);
+            double px, py;
+            int mv;
+            if (rim_walk(R, all, e, 1.0, 0.0, 1, n + 8, &px, &py, &mv) == 1) {
+                first = e;
+                double v[3];
+                rim_dir(R, px, py, v);
+                for (int j = 0; j < 3; ++j) fx[j] = o[j] + r * v[j];
             }
         }
-        int64_t g = wmin_i64(first);
+        const int64_t g = wmin_i64(first);
         if (g != INT64_MAX) {
-            int src = (int)(g - e0);
+            const int src = (int)(g - e0);
             for (int j = 0; j < 3; ++j) x[j] = __shfl(fx[j], src, 64);
             return ST_FOUND;
         }
@@ -515,8 +593,10 @@ __device__ inline int lazy_nearest(const Balls &B0, const double *o, double r, c
     double v0[3] = {g[0] / gn, g[1] / gn, g[2] / gn};
     double d0 = fabs(gn - r);
     if (d0 > bound) return 0;
-    wave_cover(B, o, r, v0, -1, &mx, &arg, &whole);
-    if (whole) return 0;
+    // a single ball holding every point of the sphere within the bound ends the search
+    int held = 0;
+    wave_cover(B, o, r, v0, -1, &mx, &arg, &whole, &held);
+    if (whole || held) return 0;
     if (!(mx > COVER_EPS)) {
         for (int j = 0; j < 3; ++j) x[j] = o[j] + r * v0[j];
         *dist_out = d0;
@@ -530,59 +610,74 @@ __device__ inline int lazy_nearest(const Balls &B0, const double *o, double r, c
     wave_sync_lds();
     double lowest = d0;  // every uncovered point is at least this far from q
     for (int round = 0; round < 8 * KMAX; ++round) {
-        double cd = INFINITY, ct_ = 0.0;
+        const SubsetCaps sub{kp, k};
+        double cd = INFINITY, cpx = 0.0, cpy = 0.0;
         int ckind = 0, crim = -1;
         Rim R, Rb;
         for (int e = lane; e < k; e += 64) {
             make_rim(kp[e], R);
             // lower bound: distance from q to the rim circle
-            double ug = dot3(R.u, g);
-            double perp = sqrt(fmax(gn * gn - ug * ug, 0.0));
-            double vg = R.c * ug + R.rho * perp;
-            double lbd = sqrt(fmax(r * r + gn * gn - 2.0 * r * vg, 0.0));
-            if (lbd <= bound) {
-                double ts = atan2(dot3(R.e2, g), dot3(R.e1, g));
-                double tp, ap, tm, am, tt = 0.0;
-                int kind_e = 0;
-                int sp = rim_walk(R, kp, k, e, ts, 1, &tp, &ap);
-                if (sp == 1 && ap == 0.0) {
-                    tt = ts;
-                    kind_e = 2;
-                } else if (sp == 1) {
-                    int sm = rim_walk(R, kp, k, e, ts, -1, &tm, &am);
-                    tt = (sm == 1 && am < ap) ? tm : tp;
-                    kind_e = 3;
-                }
-                if (kind_e) {
-                    double v[3];
-                    rim_dir(R, tt, v);
-                    double y[3] = {o[0] + r * v[0], o[1] + r * v[1], o[2] + r * v[2]};
-                    double de = dist3(y, q);
-                    if (de <= bound && de < cd) {
-                        cd = de;
-                        ct_ = tt;
-                        ckind = kind_e;
-                        crim = e;
-                        Rb = R;
-                    }
+            const double ug = dot3(R.u, g);
+            const double perp = sqrt(fmax(gn * gn - ug * ug, 0.0));
+            const double vg = R.c * ug + R.rho * perp;
+            const double lbd = sqrt(fmax(r * r + gn * gn - 2.0 * r * vg, 0.0));
+            if (!(lbd <= bound)) continue;
+            // the rim point nearest q, then the nearest uncovered one on either side
+            double sx = dot3(R.e1, g), sy = dot3(R.e2, g);
+            const double sn = sqrt(sx * sx + sy * sy);
+            if (sn > 0.0) {
+                sx /= sn;
+                sy /= sn;
+            } else {
+                sx = 1.0;
+                sy = 0.0;
+            }
+            double fx, fy, bx, by;
+            int fm, bm, kind_e = 0;
+            double tx = 0.0, ty = 0.0;
+            const int sp = rim_walk(R, sub, e, sx, sy, 1, k + 4, &fx, &fy, &fm);
+            if (sp == 1 && !fm) {
+                tx = sx;
+                ty = sy;
+                kind_e = 2;
+            } else if (sp == 1) {
+                const int sm = rim_walk(R, sub, e, sx, sy, -1, k + 4, &bx, &by, &bm);
+                const bool back = sm == 1 && pseudo_angle(bx, by, sx, sy) < pseudo_angle(sx, sy, fx, fy);
+                tx = back ? bx : fx;
+                ty = back ? by : fy;
+                kind_e = 3;
+            }
+            if (kind_e) {
+                double v[3];
+                rim_dir(R, tx, ty, v);
+                const double y[3] = {o[0] + r * v[0], o[1] + r * v[1], o[2] + r * v[2]};
+                const double de = dist3(y, q);
+                if (de <= bound && de < cd) {
+                    cd = de;
+                    cpx = tx;
+                    cpy = ty;
+                    ckind = kind_e;
+                    crim = e;
+                    Rb = R;
                 }
             }
         }
-        double best = wmin(cd);
+        const double best = wmin(cd);
         if (best == INFINITY) return 0;
         lowest = fmax(lowest, best);  // the subset-nearest distance never exceeds the true one
-        // lowest lane with the best distance
-        int64_t cand = (cd == best && ckind) ? ((int64_t)crim << 8) + lane : INT64_MAX;
-        int64_t pick = wmin_i64(cand);
-        int src = (int)(pick & 255);
-        int srim = (int)(pick >> 8);
+        // the lowest rim index with the best distance
+        const int64_t cand = (cd == best && ckind) ? ((int64_t)crim << 8) + lane : INT64_MAX;
+        const int64_t pick = wmin_i64(cand);
+        const int src = (int)(pick & 255);
+        const int srim = (int)(pick >> 8);
         double v[3] = {0.0, 0.0, 0.0};
-        if (lane == src) rim_dir(Rb, ct_, v);
+        if (lane == src) rim_dir(Rb, cpx, cpy, v);
         v[0] = __shfl(v[0], src, 64);
         v[1] = __shfl(v[1], src, 64);
         v[2] = __shfl(v[2], src, 64);
-        int kind = __shfl(ckind, src, 64);
-        wave_cover(B, o, r, v, kid[srim], &mx, &arg, &whole);
+        const int kind = __shfl(ckind, src, 64);
+        wave_cover(B, o, r, v, kid[srim], &mx, &arg, &whole, &held);
+        if (held) return 0;
         if (!(mx > COVER_EPS)) {
             for (int j = 0; j < 3; ++j) x[j] = o[j] + r * v[j];
             *dist_out = best;
@@ -604,78 +699,56 @@ __device__ inline int lazy_nearest(const Balls &B0, const double *o, double r, c
         *dist_out = lowest;
         return -1;
     }
+    const AllCaps all{&B, o, r};
     const int64_t n = ball_count(B);
     double bd = INFINITY, bx[3] = {0.0, 0.0, 0.0};
     int bkind = 0;
     double wbest = bound;  // wave-wide best so far: rims farther than it are skipped
     for (int64_t e0 = 0; e0 < n; e0 += 64) {
-      const int64_t e = e0 + lane;
-      Cap ce;
-      Rim R;
-      bool live = e < n && cap_of(B, e, o, r, ce) == 1;
-      if (live) {
-        make_rim(ce, R);
-        double ug = dot3(R.u, g);
-        double perp = sqrt(fmax(gn * gn - ug * ug, 0.0));
-        double lbd = sqrt(fmax(r * r + gn * gn - 2.0 * r * (R.c * ug + R.rho * perp), 0.0));
-        live = lbd <= wbest * (1.0 + 1e-12) + 1e-15;  // a rim farther than the best cannot win
-      }
-      if (live) {
-        double ts = atan2(dot3(R.e2, g), dot3(R.e1, g));
-        double tt[2];
-        int kinds[2] = {0, 0};
-        for (int dir = 0; dir < 2; ++dir) {
-            double t = ts, adv = 0.0;
-            for (int64_t it = 0; it < n + 8; ++it) {
-                double ct = cos(t), st = sin(t), step = 0.0;
-                bool cov = false, whole_rim = false;
-                for (int64_t f = 0; f < n; ++f) {
-                    if (f == e) continue;
-                    Cap cf;
-                    if (cap_of(B, f, o, r, cf) != 1) continue;
-                    double A, Bc, K, amp;
-                    int a = arc_of(R, cf, A, Bc, K, amp);
-                    if (a == 2) {
-                        whole_rim = true;
-                        break;
-                    }
-                    if (a == 0 || !(A * ct + Bc * st - K > ARC_EPS * amp)) continue;
-                    cov = true;
-                    double phi = atan2(Bc, A), beta = acos(fmin(1.0, fmax(-1.0, K / amp)));
-                    step = fmax(step, dir == 0 ? wrap_pos(phi + beta - t) : wrap_pos(t - (phi - beta)));
+        const int64_t e = e0 + lane;
+        Cap ce;
+        Rim R;
+        bool live = e < n && cap_of(B, e, o, r, ce) == 1;
+        if (live) {
+            make_rim(ce, R);
+            const double ug = dot3(R.u, g);
+            const double perp = sqrt(fmax(gn * gn - ug * ug, 0.0));
+            const double lbd = sqrt(fmax(r * r + gn * gn - 2.0 * r * (R.c * ug + R.rho * perp), 0.0));
+            live = lbd <= wbest * (1.0 + 1e-12) + 1e-15;  // a rim farther than the best cannot win
+        }
+        if (live) {
+            double sx = dot3(R.e1, g), sy = dot3(R.e2, g);
+            const double sn = sqrt(sx * sx + sy * sy);
+            if (sn > 0.0) {
+                sx /= sn;
+                sy /= sn;
+            } else {
+                sx = 1.0;
+                sy = 0.0;
+            }
+            for (int dir = 1; dir >= -1; dir -= 2) {
+                double px, py;
+                int mv;
+                if (rim_walk(R, all, e, sx, sy, dir, n + 8, &px, &py, &mv) != 1) continue;
+                double v[3];
+                rim_dir(R, px, py, v);
+                const double y[3] = {o[0] + r * v[0], o[1] + r * v[1], o[2] + r * v[2]};
+                const double d = dist3(y, q);
+                if (d < bd) {
+                    bd = d;
+                    bkind = mv ? 3 : 2;
+                    bx[0] = y[0];
+                    bx[1] = y[1];
+                    bx[2] = y[2];
                 }
-                if (whole_rim) break;
-                if (!cov) {
-                    tt[dir] = t;
-                    kinds[dir] = adv == 0.0 ? 2 : 3;
-                    break;
-                }
-                adv += step;
-                if (adv >= TWO_PI) break;
-                t += dir == 0 ? step : -step;
             }
         }
-        for (int dir = 0; dir < 2; ++dir) {
-            if (!kinds[dir]) continue;
-            double v[3];
-            rim_dir(R, tt[dir], v);
-            double y[3] = {o[0] + r * v[0], o[1] + r * v[1], o[2] + r * v[2]};
-            double d = dist3(y, q);
-            if (d < bd) {
-                bd = d;
-                bkind = kinds[dir];
-                bx[0] = y[0];
-                bx[1] = y[1];
-                bx[2] = y[2];
-            }
-        }
-      }
-      wbest = fmin(wbest, wmin(bd));
+        wbest = fmin(wbest, wmin(bd));
     }
-    double best = wmin(bd);
+    const double best = wmin(bd);
     if (!(best <= bound)) return 0;
-    int64_t cand = (bd == best) ? lane : INT64_MAX;
-    int src = (int)wmin_i64(cand);
+    const int64_t cand = (bd == best) ? lane : INT64_MAX;
+    const int src = (int)wmin_i64(cand);
     for (int j = 0; j < 3; ++j) x[j] = __shfl(bx[j], src, 64);
     *dist_out = best;
     return __shfl(bkind, src, 64);

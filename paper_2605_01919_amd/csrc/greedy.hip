@@ -30,11 +30,13 @@ namespace sdfi {
 
 namespace {
 
-constexpr int NW = 16;  // wavefronts per greedy work-group
+constexpr int NW = 8;  // wavefronts per greedy work-group
 constexpr int GBS = NW * 64;
 
 enum {
-    C_HI = 0, C_LO, C_ZERO, C_RMIN, C_COINC, C_INFEAS, C_UNRES, C_SEARCH, C_NUMERIC, C_NCOUNT
+    C_HI = 0, C_LO, C_ZERO, C_RMIN, C_COINC, C_INFEAS, C_UNRES, C_SEARCH, C_NUMERIC,
+    // device wall-clock ticks per sub-phase: bounds, candidates, r_min, record
+    C_T_BOUNDS, C_T_CAND, C_T_RMIN, C_T_RECORD, C_NCOUNT
 };
 
 struct GInst {
@@ -158,6 +160,7 @@ __global__ __launch_bounds__(GBS) void greedy_kernel(const GInst *insts, double 
     for (int64_t k = 0; k < m; ++k) {
         const int64_t j = I.order[k];
         const double q[3] = {I.queries[3 * j], I.queries[3 * j + 1], I.queries[3 * j + 2]};
+        unsigned long long t_mark = tid == 0 ? wall_clock64() : 0;
         // ---- cone bounds over all constraints (Sec. 4.3) ----
         double lo = -INFINITY, hi = INFINITY;
         for (int64_t c = tid; c < N; c += GBS) {
@@ -178,6 +181,11 @@ __global__ __launch_bounds__(GBS) void greedy_kernel(const GInst *insts, double 
         a = blk::bmin_i64(a, SH.S);
         b = blk::bmin_i64(b, SH.S);
         if (a == INT64_MAX || b == INT64_MAX) lo = NAN;  // only with NaN inputs
+        if (tid == 0) {
+            unsigned long long t = wall_clock64();
+            I.counts[C_T_BOUNDS] += t - t_mark;
+            t_mark = t;
+        }
         double val = NAN, wq[3] = {q[0], q[1], q[2]};
         int kindv = 0;
         int64_t act = -1;
@@ -275,6 +283,11 @@ __global__ __launch_bounds__(GBS) void greedy_kernel(const GInst *insts, double 
                     wq[2] = nw[2];
                     npend = 1;
                 }
+                if (tid == 0) {
+                    unsigned long long t = wall_clock64();
+                    I.counts[C_T_CAND] += t - t_mark;
+                    t_mark = t;
+                }
                 if (!accepted) {
                     if (lo <= tol && hi >= -tol) {
                         val = 0.0;
@@ -308,6 +321,11 @@ __global__ __launch_bounds__(GBS) void greedy_kernel(const GInst *insts, double 
                             accepted = 3;
                         } else {
                             kindv = SDFI_KIND_UNRESOLVED;
+                        }
+                        if (tid == 0) {
+                            unsigned long long t = wall_clock64();
+                            I.counts[C_T_RMIN] += t - t_mark;
+                            t_mark = t;
                         }
                     }
                 }
@@ -351,6 +369,7 @@ __global__ __launch_bounds__(GBS) void greedy_kernel(const GInst *insts, double 
         if (accepted) ++N;
         __threadfence_block();
         __syncthreads();
+        if (tid == 0) I.counts[C_T_RECORD] += wall_clock64() - t_mark;
     }
     // final witnesses of the query spheres and of the samples
     for (int64_t c = n + tid; c < N; c += GBS) {
@@ -581,6 +600,10 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
     double t3 = now_ms();
     if (report) {
         std::memset(report, 0, sizeof(*report));
+        int dev = 0, khz = 0;
+        SDFI_HIP(hipGetDevice(&dev));
+        SDFI_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+        const double wall_khz = khz > 0 ? (double)khz : 1e5;
         int64_t pairs = 0;
         for (int i = 0; i < ninst; ++i) {
             int64_t ni = soff[i + 1] - soff[i], mi = qoff[i + 1] - qoff[i];
@@ -595,6 +618,7 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
             report->n_unresolved += cc[C_UNRES];
             report->n_exact_searches += cc[C_SEARCH];
             report->n_search_capped += cc[C_NUMERIC];
+            for (int ph = 0; ph < 4; ++ph) report->ms_phase[4 + ph] += cc[C_T_BOUNDS + ph] / wall_khz;
         }
         report->pairs_evaluated = pairs;
         report->ms_phase[0] = t2 - t1;
