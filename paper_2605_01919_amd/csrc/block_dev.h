@@ -225,6 +225,7 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
         int64_t wi = INT64_MAX;
         int wk = 0, wnd = 1;
         double wlow = INFINITY;
+        geom::Holders hold;  // balls that held whole search regions (this pass's local numbering)
         const int w = wid();
         for (int guard = 0; guard < (1 << 30); ++guard) {
             int k = 0;
@@ -240,7 +241,7 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
             // prune only clearly worse spheres: exact ties must reach the tie-break
             if (lbi > cur * (1.0 + 1e-12) + 1e-15) continue;
             double d, x[3];
-            int kk = geom::lazy_nearest(L, p, fabs(p[3]), q, cur * (1.0 + 1e-12) + 1e-15, kp[w], kid[w], &d, x);
+            int kk = geom::lazy_nearest(L, p, fabs(p[3]), q, cur * (1.0 + 1e-12) + 1e-15, kp[w], kid[w], &d, x, &hold);
             if (kk < 0) {
                 // a capped search proved only that this sphere has no uncovered
                 // point nearer than d (a lower bound); it matters only if the

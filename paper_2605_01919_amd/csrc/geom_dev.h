@@ -323,13 +323,24 @@ __device__ inline int wor(int v) {
 // Balls are read U rows per lane at a time so that their loads overlap.
 constexpr double PRE_EPS = 1e-12;
 
+// Does ball f hold every point of the region of interest of sphere (o, r)?
+// The region cap (axis ru, angular radius a) lies inside the open cap of f
+// (axis u, angular radius b > a) iff angle(ru, u) < b - a, i.e.
+// ru.u > cos(b - a) = c rc + sin(b) rs; decided with a margin.
+__device__ inline bool region_held(const Balls &B, const Cap &cp) {
+    if (!(cp.c < B.rc - 1e-12)) return false;
+    const double sb = sqrt(fmax(0.0, 1.0 - cp.c * cp.c));
+    return dot3(B.ru, cp.u) > cp.c * B.rc + sb * B.rs + 1e-12;
+}
+
 __device__ inline void wave_cover(const Balls &B, const double *o, double r, const double *v, int64_t excl,
-                                  double *mx, int64_t *arg, int *whole, int *holds_region = nullptr) {
+                                  double *mx, int64_t *arg, int *whole, int *holds_region = nullptr,
+                                  int64_t *holder = nullptr) {
     constexpr int U = 4;
     const int lane = threadIdx.x & 63;
     const double x[3] = {o[0] + r * v[0], o[1] + r * v[1], o[2] + r * v[2]};
     double best = -INFINITY;
-    int64_t bi = INT64_MAX;
+    int64_t bi = INT64_MAX, hi = INT64_MAX;
     int wh = 0, hr = 0;
     const bool region = holds_region && B.use_region;
     const int64_t n = ball_count(B);
@@ -363,14 +374,13 @@ __device__ inline void wave_cover(const Balls &B, const double *o, double r, con
                 best = m;
                 bi = f;
             }
-            // the region cap (axis ru, angular radius a) lies inside this open
-            // cap (axis u, angular radius b > a) iff angle(ru, u) < b - a, i.e.
-            // ru.u > cos(b - a) = c rc + sin(b) rs; kept with a margin
-            if (region && cp.c < B.rc - 1e-12) {
-                const double sb = sqrt(fmax(0.0, 1.0 - cp.c * cp.c));
-                if (dot3(B.ru, cp.u) > cp.c * B.rc + sb * B.rs + 1e-12) hr = 1;
+            if (region && region_held(B, cp)) {
+                hr = 1;
+                hi = hi < f ? hi : f;
             }
         }
+        // a holder settles the caller's question; the margins are not needed then
+        if (holder && wor(hr)) break;
     }
     double g = wmax(best);
     int64_t cand = (best == g) ? bi : INT64_MAX;
@@ -378,6 +388,7 @@ __device__ inline void wave_cover(const Balls &B, const double *o, double r, con
     *arg = wmin_i64(cand);
     *whole = wor(wh);
     if (holds_region) *holds_region = wor(hr);
+    if (holder) *holder = wmin_i64(hi);
 }
 
 // number of caps on sphere (o, r), wave-reduced
@@ -552,12 +563,22 @@ __device__ inline int lazy_exist(const Balls &B, const double *o, double r, cons
     return ST_NONE;
 }
 
+// Recently seen balls that held a whole search region (ball indices, -1 empty).
+constexpr int NHOLD = 4;
+struct Holders {
+    int64_t h[NHOLD] = {-1, -1, -1, -1};
+    __device__ void push(int64_t f) {
+        for (int j = NHOLD - 1; j > 0; --j) h[j] = h[j - 1];
+        h[0] = f;
+    }
+};
+
 // Nearest point to q of the uncovered part of sphere (o, r) if nearer than
 // bound (strictly less or equal kept: ties are broken by the caller).
 // Returns 0 none, 1 radial foot point (T), 2 rim nearest point (D), 3 rim arc
 // end (U), -1 numeric failure; writes distance and point.
 __device__ inline int lazy_nearest(const Balls &B0, const double *o, double r, const double *q, double bound, Cap *kp,
-                                   int64_t *kid, double *dist_out, double *x) {
+                                   int64_t *kid, double *dist_out, double *x, Holders *hold = nullptr) {
     const int lane = threadIdx.x & 63;
     double g[3] = {q[0] - o[0], q[1] - o[1], q[2] - o[2]};
     double gn = sqrt(dot3(g, g));
@@ -593,9 +614,21 @@ __device__ inline int lazy_nearest(const Balls &B0, const double *o, double r, c
     double v0[3] = {g[0] / gn, g[1] / gn, g[2] / gn};
     double d0 = fabs(gn - r);
     if (d0 > bound) return 0;
-    // a single ball holding every point of the sphere within the bound ends the search
+    // a single ball holding every point of the sphere within the bound ends
+    // the search; the balls that did so recently (ball indices of B0) are
+    // tried on their own first
     int held = 0;
-    wave_cover(B, o, r, v0, -1, &mx, &arg, &whole, &held);
+    if (hold && B.use_region) {
+        for (int j = 0; j < NHOLD; ++j) {
+            if (hold->h[j] < 0) continue;
+            Cap ch;
+            const int st = cap_of(B, hold->h[j], o, r, ch);
+            if (st == 2 || (st == 1 && region_held(B, ch))) return 0;
+        }
+    }
+    int64_t hnew = INT64_MAX;
+    wave_cover(B, o, r, v0, -1, &mx, &arg, &whole, &held, hold ? &hnew : nullptr);
+    if (held && hold) hold->push(hnew);
     if (whole || held) return 0;
     if (!(mx > COVER_EPS)) {
         for (int j = 0; j < 3; ++j) x[j] = o[j] + r * v0[j];
