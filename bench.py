@@ -1,17 +1,26 @@
 """Benchmark of the hot path on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-greedy]
 
-Timed step: the dense query x sample bound sweep (float32 sweep, float64 tie
-resolution) over the workload "balls64": exact SDF of a union of 8 seeded
-balls sampled on a 64^3 grid, against all 128^3 refinement queries
-(262144 x 2097152 pairs).  Reported beside it, each timed on its own:
-  - the greedy interpolation (order, witnesses, sequential assignment,
-    certificate) of "sphere16" (16^3 samples, 32^3 queries), queries/s;
-  - the batched greedy (one launch, one work-group per instance) against the
-    same instances run one after another;
-  - the oracle's bound definition on a bounded sample on the host CPU.
-Prints one JSON line.
+Timed step (the JSON line's `value`): the dense query x sample bound
+reduction (Sec. 4.3 cone bounds with argmin/argmax, float32 sweep and float64
+tie resolution) of the workload "balls64": the exact SDF of a union of 8
+seeded balls sampled on a 64^3 grid, against all 128^3 refinement queries
+(262144 x 2097152 pairs), inputs resident in device memory.
+
+Reported beside it, each timed on its own with the device synchronised
+around it (wall clock):
+  greedy    the whole greedy interpolation (refinement order, sample
+            witnesses, sequential assignment with exact validity checks,
+            Prop. 1 certificate) of "sphere16" (16^3 samples, 32^3 queries),
+            float64 throughout, in queries/s;
+  batched   64 sphere/box union instances on uneven grids in one launch
+            (one work-group per instance) against the same 64 instances
+            run one after another through the single-instance entry;
+  cpu_baseline  the oracle's bound definition on a bounded sample of
+            balls64 queries on one host core.
+Each leg prints a progress line on stderr when it ends.  Prints one JSON
+line on stdout.
 """
 from __future__ import annotations
 
@@ -26,8 +35,16 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FLOP_PER_PAIR = 13           # 3 sub, 1 mul, 2 fma (x2), sqrt, sub, add, max, min
+# Algorithmic cost of one query-sample pair in the float32 sweep: 3 sub, 1 mul,
+# 2 fma (4 flops), sqrt, sub (s - d), add (s + d), max, min.
+FLOP_PER_PAIR = 13
 FP32_VECTOR_PEAK = 157.3e12  # MI355X published float32 vector peak, FLOP/s
+BATCH_COUNT = 64
+BATCH_GRIDS = (4, 6, 8)
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def cpu_baseline(w, sample_queries=1500):
@@ -39,8 +56,8 @@ def cpu_baseline(w, sample_queries=1500):
     dt = time.perf_counter() - t0
     pairs = sample_queries * w.n
     return {"value": round(pairs / dt / 1e9, 4), "unit": "G pair-evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sample_queries} random queries x all {w.n} samples of balls64, numpy float64, "
-                      f"one thread, {dt:.1f} s"}
+            "sample": f"{sample_queries} seeded random queries of balls64 x all {w.n} samples, numpy float64 "
+                      f"on one thread, {dt:.1f} s"}
 
 
 def timed(fn, steps, warmup):
@@ -57,6 +74,15 @@ def timed(fn, steps, warmup):
     return s.elapsed_time(e) / steps
 
 
+def wall(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,8 +92,9 @@ def main():
     ap.add_argument("--no-greedy", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the hot path runs on one "
-              "MI355X; DESIGN.md section 9 describes how it would shard)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the hot path runs on a "
+              "single MI355X (how it would shard across GPUs is described in the design notes)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -80,72 +107,75 @@ def main():
     queries = torch.tensor(w.queries, device=dev)
     n, m = w.n, w.m
 
-    lib_ms = {}
-
     def step():
         sdfi.bounds(samples, queries, "fp32")
 
-    sdfi.timing(True)
-    t0 = time.perf_counter()
-    ms = timed(step, args.steps, args.warmup)
-    wall = time.perf_counter() - t0
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    sdfi.timing(True)  # kernel timers (HIP events on the launch stream) over the timed steps only
+    ms = timed(step, args.steps, 0)
     kt = sdfi.timing_read()
     sdfi.timing(False)
     sweep_ms = kt["sweep"][0] / max(kt["sweep"][1], 1)
+    resolve_ms = kt["resolve"][0] / max(kt["resolve"][1], 1)
     pairs = n * m
     achieved = FLOP_PER_PAIR * pairs / (sweep_ms * 1e-3)
+    progress(f"bounds balls64: {ms:.2f} ms/step, sweep kernel {sweep_ms:.2f} ms, resolve {resolve_ms:.2f} ms")
     out = {
         "metric": "G query-sample bound evals/s + queries/s, batched vs plain, at 1e-5 abs",
         "value": round(pairs / (ms * 1e-3) / 1e9, 2), "unit": "G pair-evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32 sweep + f64 decisions",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32+fp64",
         "data": "synthetic",
-        "config": {"workload": "balls64", "samples": n, "queries": m, "pairs": pairs,
-                   "step": "sdfi_bounds: float32 sweep + float64 resolve"},
+        "config": {"workload": "balls64: 8-ball union SDF, 64^3 samples x 128^3 refinement queries",
+                   "samples": n, "queries": m, "pairs": pairs,
+                   "step": "sdfi_bounds: float32 sweep + float64 tie resolution"},
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 2), "peak": FP32_VECTOR_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK, 4), "traffic": None,
                      "kernel": "sweep_kernel", "kernel_ms": round(sweep_ms, 3),
                      "flop_per_launch": FLOP_PER_PAIR * pairs},
-        "wall_s": round(wall, 3),
     }
     if not args.no_greedy:
         c1 = configs.by_name("sphere16")
         s1 = torch.tensor(np.c_[c1.points, c1.values], device=dev)
         q1 = torch.tensor(c1.queries, device=dev)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        g = sdfi.greedy(s1, q1, grid=c1.grid, certify=True)
-        torch.cuda.synchronize()
-        gt = time.perf_counter() - t0
+        g, gt = wall(lambda: sdfi.greedy(s1, q1, grid=c1.grid, certify=True))
         rep = g["report"]
-        out["greedy"] = {"workload": "sphere16", "queries": c1.m, "samples": c1.n, "seconds": round(gt, 3),
-                         "queries_per_s": round(c1.m / gt, 1),
-                         "greedy_ms": round(rep["ms_phase"][2], 1), "order_ms": round(rep["ms_phase"][0], 1),
-                         "witness_ms": round(rep["ms_phase"][1], 1), "certificate_ms": round(rep["ms_phase"][3], 1),
-                         "pairs": rep["pairs_evaluated"],
-                         "violations": rep["n_violations_pairwise"] + rep["n_violations_witness"],
-                         "kinds": {"hi": rep["n_hi"], "lo": rep["n_lo"], "zero": rep["n_zero"],
-                                   "rmin": rep["n_rmin"]}}
-        inst = configs.batch(16, grids=(4, 5, 6))
+        bad = rep["n_violations_pairwise"] + rep["n_violations_witness"]
+        progress(f"greedy sphere16: {gt:.1f} s, {c1.m / gt:.0f} queries/s, violations {bad}")
+        out["greedy"] = {
+            "workload": "sphere16: sphere SDF, 16^3 samples, 32^3 refinement queries, float64",
+            "queries": c1.m, "samples": c1.n, "seconds": round(gt, 3), "queries_per_s": round(c1.m / gt, 1),
+            "ms": {"order": round(rep["ms_phase"][0], 1), "witnesses": round(rep["ms_phase"][1], 1),
+                   "greedy": round(rep["ms_phase"][2], 1), "certificate": round(rep["ms_phase"][3], 1)},
+            "device_ms": {"bounds": round(rep["ms_phase"][4], 1), "candidates": round(rep["ms_phase"][5], 1),
+                          "rmin": round(rep["ms_phase"][6], 1), "record": round(rep["ms_phase"][7], 1)},
+            "certificate_pairs": rep["pairs_evaluated"], "violations": bad,
+            "unresolved": rep["n_unresolved"], "infeasible": rep["n_infeasible"],
+            "kinds": {"hi": rep["n_hi"], "lo": rep["n_lo"], "zero": rep["n_zero"], "rmin": rep["n_rmin"],
+                      "coincident": rep["n_coincident"]}}
+        inst = configs.batch(BATCH_COUNT, grids=BATCH_GRIDS)
         tens = [(torch.tensor(np.c_[x.points, x.values], device=dev), torch.tensor(x.queries, device=dev), x.grid)
                 for x in inst]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sdfi.greedy_batched(tens)
-        torch.cuda.synchronize()
-        tb = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        for s_, q_, g_ in tens:
-            sdfi.greedy(s_, q_, grid=g_)
-        torch.cuda.synchronize()
-        tp = time.perf_counter() - t0
+        bo, tb = wall(lambda: sdfi.greedy_batched(tens))
+        progress(f"batched {BATCH_COUNT} instances: {tb:.1f} s")
+
+        def plain():
+            return [sdfi.greedy(s_, q_, grid=g_) for s_, q_, g_ in tens]
+        po, tp = wall(plain)
+        same = bool(torch.equal(torch.nan_to_num(bo["values"], nan=7.0),
+                                torch.nan_to_num(torch.cat([p["values"] for p in po]), nan=7.0)))
         mq = sum(x.m for x in inst)
-        out["batched"] = {"workload": "16 sphere/box unions, grids {4,5,6}", "queries": mq,
-                          "batched_s": round(tb, 3), "plain_s": round(tp, 3),
+        progress(f"plain {BATCH_COUNT} instances: {tp:.1f} s (batched values identical: {same})")
+        out["batched"] = {"workload": f"{BATCH_COUNT} sphere/box unions, grids drawn from {list(BATCH_GRIDS)}^3, "
+                                      "2x refinement queries",
+                          "queries": mq, "batched_s": round(tb, 3), "plain_s": round(tp, 3),
                           "batched_queries_per_s": round(mq / tb, 1), "plain_queries_per_s": round(mq / tp, 1),
-                          "speedup": round(tp / tb, 2)}
+                          "speedup": round(tp / tb, 2), "identical_values": same}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
+        progress(f"cpu baseline: {out['cpu_baseline']['value']} G pair-evals/s")
     print(json.dumps(out), flush=True)
 
 

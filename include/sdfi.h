@@ -167,7 +167,8 @@ sdfi_status sdfi_bounds(const double *samples, int64_t n, const double *queries,
  *   (i)  |s_x - s_y| <= |p_x - p_y| + tol for every pair;
  *   (ii) every witness lies on its sphere (within tol) and in no other
  *        open ball (|w - p_y| >= |s_y| - tol, with 1e-9 rounding slack).
- * Counts go to report->n_violations_pairwise / _witness and
+ * Rows whose value is NaN (queries left without a value) are not part of
+ * the set.  Counts go to report->n_violations_pairwise / _witness and
  * report->pairs_evaluated.  `report` is host memory and required;
  * synchronises the stream. */
 sdfi_status sdfi_certify(const double *pts_values, const double *witness, int64_t N, sdfi_report *report,

@@ -109,10 +109,11 @@ __device__ inline bool better(double d, int nd, double lb, int64_t i, double d2,
 // tangent spheres leave non-degenerate gaps; q counts as inside a ball when
 // d < |s| - tol.  Returns kind 0 (q in no sigma ball: radius 0),
 // 1 T, 2 D, 3 U, -1 nothing found, -2 a search hit its cap (no answer).  list: scratch of 2 (N + 1) entries;
-// kp/kid: per wave LDS scratch.
+// kp/kid: per wave LDS scratch; flist: NW lists of fcap entries (global) for exhaustive searches.
 template <int NW>
 __device__ inline int rmin_block(const double *q, int sigma, const double *p4, const double *W, int64_t N, double tol,
                                  double tie, int64_t *list, Cap (*kp)[geom::KMAX], int64_t (*kid)[geom::KMAX],
+                                 int32_t *flist, int fcap,
                                  Shared<NW> &S, double *r_out, double *x_out, int64_t *sphere_out) {
     const int tid = threadIdx.x;
     const int BS = NW * 64;
@@ -241,7 +242,7 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
             // prune only clearly worse spheres: exact ties must reach the tie-break
             if (lbi > cur * (1.0 + 1e-12) + 1e-15) continue;
             double d, x[3];
-            int kk = geom::lazy_nearest(L, p, fabs(p[3]), q, cur * (1.0 + 1e-12) + 1e-15, kp[w], kid[w], &d, x, &hold);
+            int kk = geom::lazy_nearest(L, p, fabs(p[3]), q, cur * (1.0 + 1e-12) + 1e-15, kp[w], kid[w], flist + (int64_t)w * fcap, fcap, &d, x, &hold);
             if (kk < 0) {
                 // a capped search proved only that this sphere has no uncovered
                 // point nearer than d (a lower bound); it matters only if the

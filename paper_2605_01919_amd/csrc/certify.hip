@@ -2,7 +2,9 @@
 //
 // Every pair is screened in float32; pairs whose float32 margin is within
 // eps of the threshold (eps above the float32 error of a margin) are decided
-// in float64, so the counts equal a pure float64 evaluation.
+// in float64, so the counts equal a pure float64 evaluation.  Rows whose
+// value is NaN (queries the greedy left without a value) are not part of the
+// set: every comparison with them is false and their witness is not checked.
 #include "common.h"
 
 #include <cmath>
@@ -83,7 +85,7 @@ __global__ __launch_bounds__(BT) void certify_kernel(const float4 *__restrict__ 
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
         const int64_t x = base + k * BT + tid;
-        if (x >= N) continue;
+        if (x >= N || isnan(pv[4 * x + 3])) continue;  // a row without a value is not in the set
         double w[3] = {wit[3 * x], wit[3 * x + 1], wit[3 * x + 2]};
         bool off = !(fabs(d64(w, pv + 4 * x) - fabs(pv[4 * x + 3])) <= tol);  // NaN counts as off
         if (wcov[k] || off) ++nw;

@@ -39,7 +39,8 @@ constexpr int KMAX = 128;            // working cap subset per wavefront
 constexpr double ARC_EPS = 1e-12;    // points with C.P - cos beta up to this count as uncovered
 constexpr double NUDGE = 1e-7;       // witnesses move this far (rad) off the rim they sit on
 constexpr double COVER_EPS = 1e-13;  // cover margins v.u - c up to this count as uncovered (rounding)
-constexpr int64_t FALLBACK_MAX = 4096;  // exhaustive rim walks only for spheres with at most this many caps
+constexpr int FALLBACK_LDS = 512;     // cap list of the exhaustive search held in LDS
+constexpr int FALLBACK_GLOBAL = 8192;  // cap list held in global scratch (a wavefront's share of the workspace)
 
 enum { ST_NONE = 0, ST_FOUND = 1, ST_NUMERIC = 2 };
 
@@ -193,12 +194,14 @@ struct SubsetCaps {
         return true;
     }
 };
-struct AllCaps {
+struct ListCaps {
     const Balls *B;
     const double *o;
     double r;
-    __device__ int64_t count() const { return ball_count(*B); }
-    __device__ bool get(int64_t f, Cap &c) const { return cap_of(*B, f, o, r, c) == 1; }
+    const int32_t *cl;  // ball indices of B with a cap on the sphere
+    int cnt;
+    __device__ int64_t count() const { return cnt; }
+    __device__ bool get(int64_t f, Cap &c) const { return cap_of(*B, cl[f], o, r, c) == 1; }
 };
 
 // Walk rim R over the caps of `src` (skipping index `self`) from P0 in
@@ -391,16 +394,24 @@ __device__ inline void wave_cover(const Balls &B, const double *o, double r, con
     if (holder) *holder = wmin_i64(hi);
 }
 
-// number of caps on sphere (o, r), wave-reduced
-__device__ inline int64_t wave_count_caps(const Balls &B, const double *o, double r) {
+// The indices of the balls with a cap on sphere (o, r), in index order, into
+// cl (this wave's list of ccap entries, LDS or global); returns their number,
+// which may exceed ccap (then the list holds the first ccap only).
+__device__ inline int wave_list_caps(const Balls &B, const double *o, double r, int32_t *cl, int ccap) {
     const int lane = threadIdx.x & 63;
-    int64_t cnt = 0;
+    int cnt = 0;
     const int64_t n = ball_count(B);
-    for (int64_t f = lane; f < n; f += 64) {
+    for (int64_t f0 = 0; f0 < n; f0 += 64) {
+        const int64_t f = f0 + lane;
         Cap cp;
-        if (cap_of(B, f, o, r, cp) == 1) ++cnt;
+        const int take = f < n && cap_of(B, f, o, r, cp) == 1;
+        const unsigned long long m = __ballot(take);
+        const int pos = cnt + (int)__popcll(m & ((1ull << lane) - 1ull));
+        if (take && pos < ccap) cl[pos] = (int32_t)f;
+        cnt += (int)__popcll(m);
     }
-    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+    __threadfence_block();
+    wave_sync_lds();
     return cnt;
 }
 
@@ -408,7 +419,7 @@ __device__ inline int64_t wave_count_caps(const Balls &B, const double *o, doubl
 // off the rim it was found on) to x.  kp: this wave's LDS scratch (KMAX caps),
 // kid: their ball indices.  hint orders the search only.
 __device__ inline int lazy_exist(const Balls &B, const double *o, double r, const double *hint, Cap *kp,
-                                 int64_t *kid, double *x) {
+                                 int64_t *kid, int32_t *cl, int ccap, double *x) {
     const int lane = threadIdx.x & 63;
     if (!(r > 0.0)) {
         // a sphere of radius 0 is its centre: covered iff |o - p| < |s| - tol for some ball
@@ -530,23 +541,24 @@ __device__ inline int lazy_exist(const Balls &B, const double *o, double r, cons
         wave_sync_lds();
         if (added == 0) break;  // subset full or no progress: fall back
     }
-    // Fallback: walk every rim of every cap (lanes over rims), caps recomputed.
-    // Its cost grows with the cube of the cap count, so it is bounded: beyond
-    // FALLBACK_MAX caps the search reports a numeric failure instead.
-    if (wave_count_caps(B, o, r) > FALLBACK_MAX) return ST_NUMERIC;
-    const AllCaps all{&B, o, r};
-    const int64_t n = ball_count(B);
-    for (int64_t e0 = 0; e0 < n; e0 += 64) {
-        const int64_t e = e0 + lane;
+    // Fallback: walk every rim of every cap (lanes over rims) against the
+    // listed caps.  Its cost grows with the cube of the cap count, so it is
+    // bounded by the list's size ccap: beyond it the search reports a numeric
+    // failure.
+    const int ncap = wave_list_caps(B, o, r, cl, ccap);
+    if (ncap > ccap) return ST_NUMERIC;
+    const ListCaps all{&B, o, r, cl, ncap};
+    for (int e0 = 0; e0 < ncap; e0 += 64) {
+        const int e = e0 + lane;
         int64_t first = INT64_MAX;
         double fx[3] = {0.0, 0.0, 0.0};
         Cap ce;
-        if (e < n && cap_of(B, e, o, r, ce) == 1) {
+        if (e < ncap && cap_of(B, cl[e], o, r, ce) == 1) {
             Rim R;
             make_rim(ce, R);
             double px, py;
             int mv;
-            if (rim_walk(R, all, e, 1.0, 0.0, 1, n + 8, &px, &py, &mv) == 1) {
+            if (rim_walk(R, all, e, 1.0, 0.0, 1, ncap + 8, &px, &py, &mv) == 1) {
                 first = e;
                 double v[3];
                 rim_dir(R, px, py, v);
@@ -578,7 +590,8 @@ struct Holders {
 // Returns 0 none, 1 radial foot point (T), 2 rim nearest point (D), 3 rim arc
 // end (U), -1 numeric failure; writes distance and point.
 __device__ inline int lazy_nearest(const Balls &B0, const double *o, double r, const double *q, double bound, Cap *kp,
-                                   int64_t *kid, double *dist_out, double *x, Holders *hold = nullptr) {
+                                   int64_t *kid, int32_t *cl, int ccap, double *dist_out, double *x,
+                                   Holders *hold = nullptr) {
     const int lane = threadIdx.x & 63;
     double g[3] = {q[0] - o[0], q[1] - o[1], q[2] - o[2]};
     double gn = sqrt(dot3(g, g));
@@ -602,7 +615,7 @@ __device__ inline int lazy_nearest(const Balls &B0, const double *o, double r, c
     int whole;
     if (!(gn > 0.0)) {
         if (r > bound) return 0;
-        int s = lazy_exist(B, o, r, nullptr, kp, kid, x);
+        int s = lazy_exist(B, o, r, nullptr, kp, kid, cl, ccap, x);
         if (s == ST_NUMERIC) {
             *dist_out = r;
             return -1;
@@ -726,22 +739,23 @@ __device__ inline int lazy_nearest(const Balls &B0, const double *o, double r, c
         wave_sync_lds();
         ++k;
     }
-    // Fallback: every rim against every cap (bounded as in lazy_exist).  When
-    // capped, return -1 with the last subset-nearest distance, a lower bound.
-    if (wave_count_caps(B, o, r) > FALLBACK_MAX) {
+    // Fallback: every rim against every listed cap (bounded as in
+    // lazy_exist).  When capped, return -1 with the last subset-nearest
+    // distance, a lower bound.
+    const int ncap = wave_list_caps(B, o, r, cl, ccap);
+    if (ncap > ccap) {
         *dist_out = lowest;
         return -1;
     }
-    const AllCaps all{&B, o, r};
-    const int64_t n = ball_count(B);
+    const ListCaps all{&B, o, r, cl, ncap};
     double bd = INFINITY, bx[3] = {0.0, 0.0, 0.0};
     int bkind = 0;
     double wbest = bound;  // wave-wide best so far: rims farther than it are skipped
-    for (int64_t e0 = 0; e0 < n; e0 += 64) {
-        const int64_t e = e0 + lane;
+    for (int e0 = 0; e0 < ncap; e0 += 64) {
+        const int e = e0 + lane;
         Cap ce;
         Rim R;
-        bool live = e < n && cap_of(B, e, o, r, ce) == 1;
+        bool live = e < ncap && cap_of(B, cl[e], o, r, ce) == 1;
         if (live) {
             make_rim(ce, R);
             const double ug = dot3(R.u, g);
@@ -762,7 +776,7 @@ __device__ inline int lazy_nearest(const Balls &B0, const double *o, double r, c
             for (int dir = 1; dir >= -1; dir -= 2) {
                 double px, py;
                 int mv;
-                if (rim_walk(R, all, e, sx, sy, dir, n + 8, &px, &py, &mv) != 1) continue;
+                if (rim_walk(R, all, e, sx, sy, dir, ncap + 8, &px, &py, &mv) != 1) continue;
                 double v[3];
                 rim_dir(R, px, py, v);
                 const double y[3] = {o[0] + r * v[0], o[1] + r * v[1], o[2] + r * v[2]};

@@ -54,6 +54,8 @@ struct GInst {
     double *CW;              // (n + m) x 3 witnesses
     int64_t *CSRC;           // (n + m) query index of each appended constraint
     int64_t *list;           // 2 (n + m + 1) scratch
+    int32_t *flist;          // NW cap lists of fcap entries for the exhaustive searches
+    int fcap;
     double *pend;            // (n + m) x 3 pending witness updates
     unsigned long long *counts;  // C_NCOUNT
     int64_t n, m;
@@ -126,7 +128,7 @@ __device__ void revalidate(const GInst &I, int64_t N, const double *q, double s,
             B.skip = c;
             const double *p = I.CP + 4 * c;
             double x[3];
-            int st = geom::lazy_exist(B, p, fabs(p[3]), I.CW + 3 * c, SH.kp[w], SH.kid[w], x);
+            int st = geom::lazy_exist(B, p, fabs(p[3]), I.CW + 3 * c, SH.kp[w], SH.kid[w], I.flist + (int64_t)w * I.fcap, I.fcap, x);
             if (ln == 0) {
                 atomicAdd(&I.counts[C_SEARCH], 1ull);
                 if (st == geom::ST_NUMERIC) atomicAdd(&I.counts[C_NUMERIC], 1ull);
@@ -249,7 +251,7 @@ __global__ __launch_bounds__(GBS) void greedy_kernel(const GInst *insts, double 
                             B.idx = nullptr;
         B.use_region = 0;
                             double x[3];
-                            int st = geom::lazy_exist(B, q, r, cw[e], SH.kp[0], SH.kid[0], x);
+                            int st = geom::lazy_exist(B, q, r, cw[e], SH.kp[0], SH.kid[0], I.flist, I.fcap, x);
                             if (ln == 0) {
                                 SH.status = st;
                                 SH.x[0] = x[0];
@@ -298,7 +300,7 @@ __global__ __launch_bounds__(GBS) void greedy_kernel(const GInst *insts, double 
                         int sigma = lo > tol ? 1 : -1;
                         double rr, x[3];
                         int64_t sph;
-                        int kk = blk::rmin_block<NW>(q, sigma, I.CP, I.CW, N, tol, tie, I.list, SH.kp, SH.kid, SH.S,
+                        int kk = blk::rmin_block<NW>(q, sigma, I.CP, I.CW, N, tol, tie, I.list, SH.kp, SH.kid, I.flist, I.fcap, SH.S,
                                                      &rr, x, &sph);
                         if (kk == -2 && tid == 0) atomicAdd(&I.counts[C_NUMERIC], 1ull);
                         if (kk > 0) {
@@ -386,6 +388,7 @@ __global__ __launch_bounds__(256) void witness_kernel(const double *p4, int64_t 
                                                       double *wout, uint8_t *status) {
     __shared__ geom::Cap kp[4][geom::KMAX];
     __shared__ int64_t kid[4][geom::KMAX];
+    __shared__ int32_t cl[4][geom::FALLBACK_LDS];
     const int w = threadIdx.x >> 6, ln = threadIdx.x & 63;
     for (int64_t i = (int64_t)blockIdx.x * 4 + w; i < n; i += (int64_t)gridDim.x * 4) {
         const double *pi = p4 + 4 * i;
@@ -417,7 +420,7 @@ __global__ __launch_bounds__(256) void witness_kernel(const double *p4, int64_t 
         B.idx = nullptr;
         B.use_region = 0;
         double x[3];
-        int st = geom::lazy_exist(B, pi, fabs(pi[3]), be != INT64_MAX ? p4 + 4 * be : nullptr, kp[w], kid[w], x);
+        int st = geom::lazy_exist(B, pi, fabs(pi[3]), be != INT64_MAX ? p4 + 4 * be : nullptr, kp[w], kid[w], cl[w], geom::FALLBACK_LDS, x);
         if (ln == 0) {
             status[i] = st == geom::ST_FOUND ? 1 : 0;
             for (int j = 0; j < 3; ++j) wout[3 * i + j] = st == geom::ST_FOUND ? x[j] : NAN;
@@ -428,6 +431,7 @@ __global__ __launch_bounds__(256) void witness_kernel(const double *p4, int64_t 
 struct GBufs {
     double *CP, *CW, *pend, *win;
     int64_t *CSRC, *list;
+    int32_t *flist;
     uint8_t *wstat;
     unsigned long long *counts;
     int64_t *order;
@@ -443,6 +447,7 @@ GBufs carve_greedy(Carver &c, int64_t n, int64_t m, int ninst) {
     b.win = c.take<double>(3 * (n + 1));
     b.CSRC = c.take<int64_t>(cap);
     b.list = c.take<int64_t>(2 * (cap + ninst) + 2);
+    b.flist = c.take<int32_t>((int64_t)NW * (cap + ninst));
     b.wstat = c.take<uint8_t>(n + 1);
     b.counts = c.take<unsigned long long>(C_NCOUNT * ninst);
     b.order = c.take<int64_t>(m + 1);
@@ -562,7 +567,7 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
     double t2 = now_ms();
     // 3. greedy, one work-group per instance
     std::vector<GInst> hi(ninst);
-    int64_t cpos = 0;
+    int64_t cpos = 0, fpos = 0;
     for (int i = 0; i < ninst; ++i) {
         GInst &g = hi[i];
         int64_t ni = soff[i + 1] - soff[i], mi = qoff[i + 1] - qoff[i];
@@ -583,6 +588,10 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
         g.pend = b.pend + 3 * cpos;
         g.CSRC = b.CSRC + cpos;
         g.list = b.list + 2 * (cpos + i);
+        // each wave's cap list holds every ball of a small instance, FALLBACK_GLOBAL otherwise
+        g.fcap = (int)std::min<int64_t>(geom::FALLBACK_GLOBAL, ni + mi + 1);
+        g.flist = b.flist + fpos;
+        fpos += (int64_t)NW * g.fcap;
         g.counts = b.counts + C_NCOUNT * i;
         g.n = ni;
         g.m = mi;

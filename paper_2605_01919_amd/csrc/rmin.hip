@@ -35,9 +35,10 @@ struct RShared {
 __global__ __launch_bounds__(RBS) void rmin_kernel(const double *pts, const int8_t *force, const double *keep,
                                                    int64_t K, const double *p4, const double *W, int64_t nb,
                                                    double tol, double tie, double *val, uint8_t *kind, double *wout,
-                                                   int64_t *lists) {
+                                                   int64_t *lists, int32_t *flists, int fcap) {
     __shared__ RShared SH;
     int64_t *list = lists + (int64_t)blockIdx.x * 2 * (nb + 1);
+    int32_t *flist = flists + (int64_t)blockIdx.x * RW * fcap;
     for (int64_t k = blockIdx.x; k < K; k += gridDim.x) {
         const double q[3] = {pts[3 * k], pts[3 * k + 1], pts[3 * k + 2]};
         int sigma = force ? force[k] : 0;
@@ -63,7 +64,7 @@ __global__ __launch_bounds__(RBS) void rmin_kernel(const double *pts, const int8
         double r = 0.0, x[3] = {q[0], q[1], q[2]};
         int64_t sph = -1;
         int kk = sigma == 0 ? 0
-                            : blk::rmin_block<RW>(q, sigma, p4, W, nb, tol, tie, list, SH.kp, SH.kid, SH.S, &r, x,
+                            : blk::rmin_block<RW>(q, sigma, p4, W, nb, tol, tie, list, SH.kp, SH.kid, flist, fcap, SH.S, &r, x,
                                                   &sph);
         if (threadIdx.x == 0) {
             bool forced = force && force[k] != 0;
@@ -126,17 +127,22 @@ __global__ void scatter_repair_kernel(const int64_t *ridx, int64_t nr, const dou
     }
 }
 
+int flist_cap(int64_t nb) { return (int)std::min<int64_t>(geom::FALLBACK_GLOBAL, nb + 1); }
+
 double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
 sdfi_status launch_rmin(const double *pts, const int8_t *force, const double *keep, int64_t K, const double *p4,
                         const double *W, int64_t nb, const sdfi_options &o, double *val, uint8_t *kind, double *wout,
-                        int64_t *lists, hipStream_t st) {
+                        int64_t *lists, int32_t *flists, hipStream_t st) {
     if (K == 0) return SDFI_OK;
     int grid = (int)std::min<int64_t>(K, RGRID);
+    // each wave's cap list for exhaustive searches: every ball of a small set, FALLBACK_GLOBAL otherwise
+    const int fcap = flist_cap(nb);
     KernelTimer tm("rmin", st);
-    rmin_kernel<<<grid, RBS, 0, st>>>(pts, force, keep, K, p4, W, nb, o.tol, o.tie_tol, val, kind, wout, lists);
+    rmin_kernel<<<grid, RBS, 0, st>>>(pts, force, keep, K, p4, W, nb, o.tol, o.tie_tol, val, kind, wout, lists,
+                                      flists, fcap);
     tm.stop();
     SDFI_HIP(hipGetLastError());
     return SDFI_OK;
@@ -149,6 +155,7 @@ size_t rmin_ws(int64_t n, int64_t m, const sdfi_options &) {
     c.take<double>(3 * (n + 1));                  // witnesses
     c.take<uint8_t>(n + 1);                       // status
     c.take<int64_t>((size_t)RGRID * 2 * (n + 1)); // per work-group lists
+    c.take<int32_t>((size_t)RGRID * RW * flist_cap(n)); // per wave cap lists
     return c.used + 1024;
 }
 
@@ -167,6 +174,7 @@ size_t repair_ws(int64_t n, int64_t m, const sdfi_options &) {
     c.take<uint8_t>(n + 1);                       // their kinds
     c.take<double>(3 * (n + m + 1));              // contact points
     c.take<int64_t>((size_t)RGRID * 2 * (n + 1)); // per work-group lists
+    c.take<int32_t>((size_t)RGRID * RW * flist_cap(n)); // per wave cap lists
     return c.used + 4096;
 }
 
@@ -192,9 +200,10 @@ extern "C" sdfi_status sdfi_min_valid_radius(const double *samples, int64_t n, c
     double *W = c.take<double>(3 * (n + 1));
     uint8_t *wst = c.take<uint8_t>(n + 1);
     int64_t *lists = c.take<int64_t>((size_t)RGRID * 2 * (n + 1));
+    int32_t *flists = c.take<int32_t>((size_t)RGRID * RW * flist_cap(n));
     s = run_witnesses(samples, n, W, wst, o, st);
     if (s != SDFI_OK) return s;
-    return launch_rmin(queries, nullptr, nullptr, m, samples, W, n, o, values, kind, witness, lists, st);
+    return launch_rmin(queries, nullptr, nullptr, m, samples, W, n, o, values, kind, witness, lists, flists, st);
 }
 
 extern "C" sdfi_status sdfi_repair(const double *samples, int64_t n, const double *queries, int64_t m,
@@ -226,6 +235,7 @@ extern "C" sdfi_status sdfi_repair(const double *samples, int64_t n, const doubl
     uint8_t *rkind = c.take<uint8_t>(n + 1);
     double *contact = c.take<double>(3 * (n + m + 1));
     int64_t *lists = c.take<int64_t>((size_t)RGRID * 2 * (n + 1));
+    int32_t *flists = c.take<int32_t>((size_t)RGRID * RW * flist_cap(n));
     double t0 = now_ms();
     // 1. fully covered samples (Prop. 1 (ii) fails): no witness against all inputs
     s = run_witnesses(samples, n, W, wst, o, st);
@@ -251,9 +261,10 @@ extern "C" sdfi_status sdfi_repair(const double *samples, int64_t n, const doubl
     SDFI_HIP(hipGetLastError());
     double t2 = now_ms();
     // 3. minimum valid radii of the removed points (their sign) and of the queries
-    s = launch_rmin(rpts, rforce, rkeep, nr, bp, bw, nk, o, rval, rkind, contact, lists, st);
+    s = launch_rmin(rpts, rforce, rkeep, nr, bp, bw, nk, o, rval, rkind, contact, lists, flists, st);
     if (s != SDFI_OK) return s;
-    s = launch_rmin(queries, nullptr, nullptr, m, bp, bw, nk, o, query_values, kind + n, contact + 3 * nr, lists, st);
+    s = launch_rmin(queries, nullptr, nullptr, m, bp, bw, nk, o, query_values, kind + n, contact + 3 * nr, lists,
+                    flists, st);
     if (s != SDFI_OK) return s;
     init_repair_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(samples, n, wst, repaired, removed, kind);
     if (nr)
