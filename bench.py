@@ -1,6 +1,6 @@
 """Benchmark of the hot path on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-greedy]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-greedy] [--no-batched]
 
 Timed step (the JSON line's `value`): the dense query x sample bound
 reduction (Sec. 4.3 cone bounds with argmin/argmax, float32 sweep and float64
@@ -40,14 +40,14 @@ sys.path.insert(0, ROOT)
 FLOP_PER_PAIR = 13
 FP32_VECTOR_PEAK = 157.3e12  # MI355X published float32 vector peak, FLOP/s
 BATCH_COUNT = 64
-BATCH_GRIDS = (4, 6, 8)
+BATCH_GRIDS = (4, 5, 6)
 
 
 def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, sample_queries=1500):
+def cpu_baseline(w, sample_queries=4500):
     """The oracle's bound definition timed on a bounded sample of queries."""
     from oracle import bounds as OB
     q = w.queries[np.random.default_rng(0).choice(w.m, sample_queries, replace=False)]
@@ -90,6 +90,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-greedy", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the hot path runs on a "
@@ -155,6 +156,7 @@ def main():
             "unresolved": rep["n_unresolved"], "infeasible": rep["n_infeasible"],
             "kinds": {"hi": rep["n_hi"], "lo": rep["n_lo"], "zero": rep["n_zero"], "rmin": rep["n_rmin"],
                       "coincident": rep["n_coincident"]}}
+    if not args.no_greedy and not args.no_batched:
         inst = configs.batch(BATCH_COUNT, grids=BATCH_GRIDS)
         tens = [(torch.tensor(np.c_[x.points, x.values], device=dev), torch.tensor(x.queries, device=dev), x.grid)
                 for x in inst]
