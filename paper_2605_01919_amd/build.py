@@ -14,6 +14,8 @@ FLAGS = [
     # no packed float32 instructions anywhere (some forms are unreliable on
     # this hardware); hipcc -O3 would otherwise emit them from plain code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core results in ordinary VGPRs (no accumulation-register round trip)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-fno-gpu-rdc", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 

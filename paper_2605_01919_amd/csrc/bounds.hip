@@ -16,7 +16,21 @@
 // Pass 2 (resolve): one wavefront per query recomputes its listed tiles in
 // float64 (or all samples after an overflow), takes the exact extreme and
 // the smallest index within tie_tol of it, and writes the flags.
+//
+// float32 mode runs pass 1 on spatially sorted data (Morton order of samples
+// and of queries, so a tile and a work-group's 256 queries are compact
+// boxes).  For a tile whose box is far from the work-group's query box the
+// squared distances come from the matrix cores as one product per 16x16
+// block, |p - q|^2 = |a|^2 - 2 a.b + |b|^2 with a = p - c, b = q - c and c the
+// query box centre (v_mfma_f32_16x16x4f32: A = (-2a, |a|^2) per sample,
+// B = (b, 1) per query, C = |b|^2); near tiles use the direct float32
+// formula.  The far tiles' extra rounding is bounded from the data's extent
+// and the box separation, and the candidate band eps (computed on the device
+// from the data's magnitudes) covers both paths, so the float64 resolve sees
+// every sample that can reach the tie band.
 #include "common.h"
+
+#include <hipcub/hipcub.hpp>
 
 #include <cfloat>
 #include <cmath>
@@ -198,15 +212,19 @@ __device__ inline int wave_sum(int v) {
 
 __device__ inline int sign_class(double s, double tie) { return s > tie ? 1 : (s < -tie ? -1 : 0); }
 
+// sperm (nullable): tile t holds the samples sperm[t*TILE ...] (sorted order);
+// eps_dev (nullable): the band, computed on the device, replaces eps.
 template <typename T>
 __global__ __launch_bounds__(256) void resolve_kernel(const double *__restrict__ samples, int64_t n,
                                                       const double *__restrict__ queries, int64_t m, T eps,
                                                       SweepOut<T> o, double tol, double tie, double *lo_out,
                                                       double *hi_out, int32_t *argmax, int32_t *argmin,
-                                                      uint32_t *flags, int64_t *overflows) {
+                                                      uint32_t *flags, int64_t *overflows,
+                                                      const int32_t *__restrict__ sperm, const float *eps_dev) {
     const int lane = threadIdx.x & 63;
     const int64_t qi = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
     if (qi >= m) return;
+    if (eps_dev) eps = (T)*eps_dev;
     const double q[3] = {queries[3 * qi], queries[3 * qi + 1], queries[3 * qi + 2]};
     double ext[2];
     int64_t arg[2];
@@ -232,7 +250,8 @@ __global__ __launch_bounds__(256) void resolve_kernel(const double *__restrict__
             for (int j = lane; j < TILE; j += 64) {
                 int64_t i = (int64_t)t * TILE + j;
                 if (i < n) {
-                    double v = pair_val(samples + 4 * i, q, side);
+                    const int64_t oi = sperm ? (int64_t)sperm[i] : i;
+                    double v = pair_val(samples + 4 * oi, q, side);
                     best = side == 0 ? fmax(best, v) : fmin(best, v);
                 }
             }
@@ -254,11 +273,12 @@ __global__ __launch_bounds__(256) void resolve_kernel(const double *__restrict__
             for (int j = lane; j < TILE; j += 64) {
                 int64_t i = (int64_t)t * TILE + j;
                 if (i < n) {
-                    double v = pair_val(samples + 4 * i, q, side);
+                    const int64_t oi = sperm ? (int64_t)sperm[i] : i;
+                    double v = pair_val(samples + 4 * oi, q, side);
                     bool in = side == 0 ? (v >= best - tie) : (v <= best + tie);
                     if (in) {
                         inband++;
-                        first = i < first ? i : first;
+                        first = oi < first ? oi : first;
                     }
                 }
             }
@@ -286,6 +306,373 @@ __global__ __launch_bounds__(256) void resolve_kernel(const double *__restrict__
         if (have_a && sign_class(lo, tie) * sign_class(samples[4 * arg[0] + 3], tie) < 0) f |= SDFI_FLAG_LO_OPPOSITE;
         flags[qi] = f;
     }
+}
+
+// ---- float32 sweep over spatially sorted data ----
+
+constexpr int MQ = 256;             // queries per work-group of the sorted sweep (4 wavefronts x 64)
+constexpr int EXT_BLOCKS = 256;     // partial reductions of the extent
+constexpr float U32 = 5.9604645e-8f;  // unit roundoff of float32
+
+// Extent of samples and queries and the constants derived from it.
+struct Extent {
+    float lo[4], hi[4];  // bounding box (float32 coordinates)
+    float mc, ms;        // largest |coordinate| and |value|
+    float eps;           // candidate band of the sweep
+    float rho_cap;       // largest query-box radius that may use the matrix path
+    float delta0;        // smallest box gap of a matrix-path tile
+    float pad[3];
+};
+
+struct ExtPart {
+    float lo[3], hi[3], mc, ms;
+};
+
+__device__ inline float wred_min(float v) {
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ inline float wred_max(float v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// per-block partial extents over samples (n x 4) and queries (m x 3)
+__global__ __launch_bounds__(256) void extent_partial_kernel(const double *__restrict__ samples, int64_t n,
+                                                             const double *__restrict__ queries, int64_t m,
+                                                             ExtPart *parts) {
+    __shared__ float red[8][4];
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    float mc = 0.0f, ms = 0.0f;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n + m; i += stride) {
+        const double *p = i < n ? samples + 4 * i : queries + 3 * (i - n);
+        for (int k = 0; k < 3; ++k) {
+            const float x = (float)p[k];
+            lo[k] = fminf(lo[k], x);
+            hi[k] = fmaxf(hi[k], x);
+            mc = fmaxf(mc, fabsf(x));
+        }
+        if (i < n) ms = fmaxf(ms, fabsf((float)p[3]));
+    }
+    float v[8] = {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], mc, ms};
+    for (int k = 0; k < 8; ++k) v[k] = k < 3 ? wred_min(v[k]) : wred_max(v[k]);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __shared__ float wv[4][8];
+    if (lane == 0)
+        for (int k = 0; k < 8; ++k) wv[w][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ExtPart e;
+        for (int k = 0; k < 3; ++k) {
+            e.lo[k] = fminf(fminf(wv[0][k], wv[1][k]), fminf(wv[2][k], wv[3][k]));
+            e.hi[k] = fmaxf(fmaxf(wv[0][3 + k], wv[1][3 + k]), fmaxf(wv[2][3 + k], wv[3][3 + k]));
+        }
+        e.mc = fmaxf(fmaxf(wv[0][6], wv[1][6]), fmaxf(wv[2][6], wv[3][6]));
+        e.ms = fmaxf(fmaxf(wv[0][7], wv[1][7]), fmaxf(wv[2][7], wv[3][7]));
+        parts[blockIdx.x] = e;
+    }
+    (void)red;
+}
+
+// Final extent and the band.  Error of one float32 pair value s - d or s + d
+// against its float64 value (u the unit roundoff, Mc/Ms the largest
+// coordinate/value magnitudes, E the extent's diagonal):
+//   direct formula: inputs rounded (2 sqrt3 u Mc on d, u Ms on s), three
+//     differences, squares and sum (5u relative on d^2), sqrt (1 ulp) and the
+//     final add: at most u (2 Ms + 23 Mc);
+//   matrix path: the same input rounding plus the product form of d^2, whose
+//     error is at most 8u (|a| + |b|)^2 <= 8u (d + 2 rho)^2 with rho the query
+//     box radius; for a tile at box gap d >= max(delta0, 2 rho) and d <= E it
+//     perturbs d by at most 8u (E + 6 rho) (+ rounding of the centring and of
+//     the sqrt), so with rho <= rho_cap = E/16 the value errs by at most
+//     u (11 E + 50 rho_cap + 7 Mc + 2 Ms).
+// Two values may err in opposite directions: eps = tie + 2.5 x the larger.
+__global__ void extent_final_kernel(const ExtPart *parts, int np, double tie, Extent *out) {
+    if (threadIdx.x != 0) return;
+    Extent e;
+    for (int k = 0; k < 3; ++k) {
+        e.lo[k] = INFINITY;
+        e.hi[k] = -INFINITY;
+    }
+    e.lo[3] = e.hi[3] = 0.0f;
+    e.mc = e.ms = 0.0f;
+    for (int i = 0; i < np; ++i) {
+        for (int k = 0; k < 3; ++k) {
+            e.lo[k] = fminf(e.lo[k], parts[i].lo[k]);
+            e.hi[k] = fmaxf(e.hi[k], parts[i].hi[k]);
+        }
+        e.mc = fmaxf(e.mc, parts[i].mc);
+        e.ms = fmaxf(e.ms, parts[i].ms);
+    }
+    float d2 = 0.0f;
+    for (int k = 0; k < 3; ++k) d2 += (e.hi[k] - e.lo[k]) * (e.hi[k] - e.lo[k]);
+    const float E = sqrtf(d2) * 1.0001f;
+    e.rho_cap = E / 16.0f;
+    e.delta0 = E / 64.0f;
+    const float near_err = U32 * (2.0f * e.ms + 23.0f * e.mc);
+    const float far_err = U32 * (11.0f * E + 50.0f * e.rho_cap + 7.0f * e.mc + 2.0f * e.ms);
+    e.eps = (float)tie + 2.5f * fmaxf(near_err, far_err);
+    e.pad[0] = e.pad[1] = e.pad[2] = 0.0f;
+    *out = e;
+}
+
+__device__ inline uint32_t spread10(uint32_t v) {
+    v &= 1023u;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+// Morton keys (10 bits per axis over the extent's box) of rows of `pts`
+// (stride 3 or 4 doubles) and the identity permutation.
+__global__ void morton_kernel(const double *__restrict__ pts, int stride, int64_t k, const Extent *ext,
+                              uint32_t *keys, int32_t *idx) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= k) return;
+    uint32_t c[3];
+    for (int a = 0; a < 3; ++a) {
+        const float span = ext->hi[a] - ext->lo[a];
+        const float t = span > 0.0f ? ((float)pts[stride * i + a] - ext->lo[a]) / span : 0.0f;
+        const float f = fminf(fmaxf(t * 1024.0f, 0.0f), 1023.0f);  // NaN -> 0
+        c[a] = (uint32_t)f;
+    }
+    keys[i] = spread10(c[0]) | (spread10(c[1]) << 1) | (spread10(c[2]) << 2);
+    idx[i] = (int32_t)i;
+}
+
+// float32 copy of the samples in sorted order
+__global__ void pack_sorted_kernel(const double *__restrict__ samples, const int32_t *__restrict__ perm, int64_t n,
+                                   float4 *__restrict__ out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) {
+        const double *p = samples + 4 * (int64_t)perm[i];
+        out[i] = make_float4((float)p[0], (float)p[1], (float)p[2], (float)p[3]);
+    }
+}
+
+// box of each tile of the sorted samples: tbox[2t] = low corner, tbox[2t+1] = high corner
+__global__ __launch_bounds__(TILE) void tile_box_kernel(const float4 *__restrict__ ps, int64_t n, float4 *tbox) {
+    __shared__ float wv[TILE / 64][6];
+    const int64_t i = (int64_t)blockIdx.x * TILE + threadIdx.x;
+    float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    if (i < n) {
+        const float4 p = ps[i];
+        v[0] = v[3] = p.x;
+        v[1] = v[4] = p.y;
+        v[2] = v[5] = p.z;
+    }
+    for (int k = 0; k < 6; ++k) v[k] = k < 3 ? wred_min(v[k]) : wred_max(v[k]);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 6; ++k) wv[w][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int ww = 1; ww < TILE / 64; ++ww)
+            for (int k = 0; k < 6; ++k) wv[0][k] = k < 3 ? fminf(wv[0][k], wv[ww][k]) : fmaxf(wv[0][k], wv[ww][k]);
+        tbox[2 * blockIdx.x] = make_float4(wv[0][0], wv[0][1], wv[0][2], 0.0f);
+        tbox[2 * blockIdx.x + 1] = make_float4(wv[0][3], wv[0][4], wv[0][5], 0.0f);
+    }
+}
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// One work-group: 256 consecutive queries of the sorted order (lane l of
+// wavefront w owns sorted query 256 b + 64 w + l), all sample tiles.
+__global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restrict__ ps, int n,
+                                                          const float4 *__restrict__ tbox,
+                                                          const double *__restrict__ queries,
+                                                          const int32_t *__restrict__ qperm, int64_t m,
+                                                          const Extent *__restrict__ ext, SweepOut<float> o) {
+    __shared__ float4 raw[TILE];  // tile samples (x, y, z, s)
+    __shared__ float4 cen[TILE];  // (-2 a, |a|^2) with a = p - c
+    __shared__ float sv[TILE];    // tile values
+    __shared__ float wbox[MQ / 64][6];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t sq = (int64_t)blockIdx.x * MQ + tid;
+    const bool valid = sq < m;
+    const int64_t qi = qperm[valid ? sq : (int64_t)blockIdx.x * MQ];  // original index (a stand-in when past m)
+    const float qx = (float)queries[3 * qi], qy = (float)queries[3 * qi + 1], qz = (float)queries[3 * qi + 2];
+    // the work-group's query box, its centre and radius
+    float v[6] = {qx, qy, qz, qx, qy, qz};
+    for (int k = 0; k < 6; ++k) v[k] = k < 3 ? wred_min(v[k]) : wred_max(v[k]);
+    if (lane == 0)
+        for (int k = 0; k < 6; ++k) wbox[w][k] = v[k];
+    __syncthreads();
+    float qlo[3], qhi[3];
+    for (int k = 0; k < 3; ++k) {
+        qlo[k] = fminf(fminf(wbox[0][k], wbox[1][k]), fminf(wbox[2][k], wbox[3][k]));
+        qhi[k] = fmaxf(fmaxf(wbox[0][3 + k], wbox[1][3 + k]), fmaxf(wbox[2][3 + k], wbox[3][3 + k]));
+    }
+    const float cx = 0.5f * (qlo[0] + qhi[0]), cy = 0.5f * (qlo[1] + qhi[1]), cz = 0.5f * (qlo[2] + qhi[2]);
+    float r2 = 0.0f;
+    for (int k = 0; k < 3; ++k) r2 += (qhi[k] - qlo[k]) * (qhi[k] - qlo[k]);
+    const float rho = 0.5f * sqrtf(r2) * 1.0001f;
+    const float eps = ext->eps;
+    const bool far_ok = rho <= ext->rho_cap;
+    const float delta = fmaxf(ext->delta0, 2.0f * rho);
+    // matrix operands of this wave's queries: column block cb holds local
+    // queries 16 cb + (lane & 15); this lane supplies component lane >> 4
+    const float bx = qx - cx, by = qy - cy, bz = qz - cz;
+    const float bb = bx * bx + by * by + bz * bz;
+    float B[4];
+    f32x4 C[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+        const int src = 16 * cb + (lane & 15);
+        const float x_ = __shfl(bx, src, 64), y_ = __shfl(by, src, 64), z_ = __shfl(bz, src, 64);
+        const float b2 = __shfl(bb, src, 64);
+        const int k = lane >> 4;
+        B[cb] = k == 0 ? x_ : (k == 1 ? y_ : (k == 2 ? z_ : 1.0f));
+        C[cb] = f32x4{b2, b2, b2, b2};
+    }
+    float run_lo = -INFINITY, run_hi = INFINITY;
+    uint32_t clo = 0, chi = 0;
+    const int ntiles = (n + TILE - 1) / TILE;
+    // Two passes over the tiles: the near ones first (direct formula), so that
+    // the running extremes are already close to final when the far tiles are
+    // swept on the matrix path and its group test can skip most square roots.
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int t = 0; t < ntiles; ++t) {
+            const int cnt = min(TILE, n - t * TILE);
+            const float4 tl = tbox[2 * t], th = tbox[2 * t + 1];
+            const float gx = fmaxf(0.0f, fmaxf(tl.x - qhi[0], qlo[0] - th.x));
+            const float gy = fmaxf(0.0f, fmaxf(tl.y - qhi[1], qlo[1] - th.y));
+            const float gz = fmaxf(0.0f, fmaxf(tl.z - qhi[2], qlo[2] - th.z));
+            const float gap = sqrtf(gx * gx + gy * gy + gz * gz);
+            const bool far = far_ok && cnt == TILE && gap > 0.0f && gap >= delta;
+            if (far != (pass == 1)) continue;  // uniform over the work-group
+            __syncthreads();
+            if (tid < cnt) {
+                const float4 p = ps[(int64_t)t * TILE + tid];
+                raw[tid] = p;
+                if (far) {
+                    const float ax = p.x - cx, ay = p.y - cy, az = p.z - cz;
+                    cen[tid] = make_float4(-2.0f * ax, -2.0f * ay, -2.0f * az, ax * ax + ay * ay + az * az);
+                    sv[tid] = p.w;
+                }
+            }
+            __syncthreads();
+            float tlo = -INFINITY, thi = INFINITY;
+            if (far) {
+                // Running extremes of the four query columns this lane holds, widened
+                // by 2 eps.  A pair with d >= max(s - rl, rh - s) has s - d <= rl and
+                // s + d >= rh: it can neither be near either extreme nor move it, so a
+                // 16 x 16 block where every lane has min d^2 >= T^2 (T built from its
+                // four samples' largest and smallest value) needs no square root.
+                float rl[4], rh[4];
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) {
+                    const int src = 16 * cb + (lane & 15);
+                    rl[cb] = __shfl(run_lo, src, 64) - 2.0f * eps;
+                    rh[cb] = __shfl(run_hi, src, 64) + 2.0f * eps;
+                }
+                float lo4[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+                float hi4[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+                const float *cenf = reinterpret_cast<const float *>(cen);
+#pragma unroll 2
+                for (int b = 0; b < TILE / 16; ++b) {
+                    // A[i][k]: sample 16 b + i, component k (this lane: i = lane & 15, k = lane >> 4)
+                    const float a = cenf[4 * (16 * b + (lane & 15)) + (lane >> 4)];
+                    // rows of the product held by this lane: samples 16 b + 4 (lane >> 4) + 0..3
+                    const float4 s4 = *reinterpret_cast<const float4 *>(&sv[16 * b + 4 * (lane >> 4)]);
+                    f32x4 D[4];
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb)
+                        D[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, B[cb], C[cb], 0, 0, 0);
+                    const float smax = fmaxf(fmaxf(s4.x, s4.y), fmaxf(s4.z, s4.w));
+                    const float smin = fminf(fminf(s4.x, s4.y), fminf(s4.z, s4.w));
+                    int need = 0;
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb) {
+                        const float dmin2 = fminf(fminf(D[cb][0], D[cb][1]), fminf(D[cb][2], D[cb][3]));
+                        const float T = fmaxf(fmaxf(smax - rl[cb], rh[cb] - smin), 0.0f);
+                        need |= dmin2 < T * T;
+                    }
+                    if (__any(need)) {
+#pragma unroll
+                        for (int cb = 0; cb < 4; ++cb) {
+                            const float d0 = __builtin_amdgcn_sqrtf(fabsf(D[cb][0]));
+                            const float d1 = __builtin_amdgcn_sqrtf(fabsf(D[cb][1]));
+                            const float d2 = __builtin_amdgcn_sqrtf(fabsf(D[cb][2]));
+                            const float d3 = __builtin_amdgcn_sqrtf(fabsf(D[cb][3]));
+                            lo4[cb] = fmaxf(fmaxf(lo4[cb], s4.x - d0), s4.y - d1);
+                            lo4[cb] = fmaxf(fmaxf(lo4[cb], s4.z - d2), s4.w - d3);
+                            hi4[cb] = fminf(fminf(hi4[cb], s4.x + d0), s4.y + d1);
+                            hi4[cb] = fminf(fminf(hi4[cb], s4.z + d2), s4.w + d3);
+                        }
+                    }
+                }
+                // combine the four row groups holding each query column
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) {
+                    lo4[cb] = fmaxf(lo4[cb], __shfl_xor(lo4[cb], 16, 64));
+                    lo4[cb] = fmaxf(lo4[cb], __shfl_xor(lo4[cb], 32, 64));
+                    hi4[cb] = fminf(hi4[cb], __shfl_xor(hi4[cb], 16, 64));
+                    hi4[cb] = fminf(hi4[cb], __shfl_xor(hi4[cb], 32, 64));
+                }
+                // this lane's own query is local query `lane`: column block lane >> 4
+                const int mine = lane >> 4;
+                tlo = mine == 0 ? lo4[0] : (mine == 1 ? lo4[1] : (mine == 2 ? lo4[2] : lo4[3]));
+                thi = mine == 0 ? hi4[0] : (mine == 1 ? hi4[1] : (mine == 2 ? hi4[2] : hi4[3]));
+            } else {
+                for (int j = 0; j < cnt; ++j) {
+                    const float4 p = raw[j];
+                    const float dx = qx - p.x, dy = qy - p.y, dz = qz - p.z;
+                    const float d = __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz);
+                    tlo = fmaxf(tlo, p.w - d);
+                    thi = fminf(thi, p.w + d);
+                }
+            }
+            if (valid) {
+                note_tile<float>(0, qi, t, tlo, run_lo, clo, eps, o);
+                note_tile<float>(1, qi, t, thi, run_hi, chi, eps, o);
+            }
+        }
+    }
+    if (valid) {
+        o.run[2 * qi] = run_lo;
+        o.run[2 * qi + 1] = run_hi;
+        o.count[2 * qi] = clo;
+        o.count[2 * qi + 1] = chi;
+    }
+}
+
+// workspace of the sorted float32 path
+struct SortedBufs {
+    ExtPart *parts;
+    Extent *ext;
+    uint32_t *keys_in, *keys_out;
+    int32_t *idx_in, *sperm, *qperm;
+    float4 *ps, *tbox;
+    void *cub;
+    size_t cub_bytes;
+};
+
+size_t cub_sort_bytes(int64_t k) {
+    size_t bytes = 0;
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                                            (const int32_t *)nullptr, (int32_t *)nullptr, (int)k, 0, 30);
+    return bytes;
+}
+
+SortedBufs carve_sorted(Carver &c, int64_t n, int64_t m) {
+    SortedBufs b;
+    const int64_t k = n > m ? n : m;
+    b.parts = c.take<ExtPart>(EXT_BLOCKS);
+    b.ext = c.take<Extent>(1);
+    b.keys_in = c.take<uint32_t>(k);
+    b.keys_out = c.take<uint32_t>(k);
+    b.idx_in = c.take<int32_t>(k);
+    b.sperm = c.take<int32_t>(n);
+    b.qperm = c.take<int32_t>(m);
+    b.ps = c.take<float4>(n);
+    b.tbox = c.take<float4>(2 * ((n + TILE - 1) / TILE));
+    b.cub_bytes = std::max(cub_sort_bytes(n), cub_sort_bytes(m));
+    b.cub = c.take<char>(b.cub_bytes);
+    return b;
 }
 
 template <typename T>
@@ -332,7 +719,46 @@ sdfi_status launch(const double *samples, int64_t n, const double *queries, int6
     KernelTimer t2("resolve", st);
     resolve_kernel<T><<<(unsigned)((m + 3) / 4), 256, 0, st>>>(samples, n, queries, m, eps, b.o, opt.tol,
                                                                 opt.tie_tol, lo, hi, argmax, argmin, flags,
-                                                                b.overflows);
+                                                                b.overflows, nullptr, nullptr);
+    t2.stop();
+    SDFI_HIP(hipGetLastError());
+    if (overflow_count) {
+        SDFI_HIP(hipMemcpyAsync(overflow_count, b.overflows, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    }
+    return SDFI_OK;
+}
+
+sdfi_status launch_sorted(const double *samples, int64_t n, const double *queries, int64_t m, double *lo,
+                          double *hi, int32_t *argmax, int32_t *argmin, uint32_t *flags, Carver &ws,
+                          const sdfi_options &opt, hipStream_t st, int64_t *overflow_count) {
+    SweepBufs<float> b = carve_sweep<float>(ws, n, m);
+    SortedBufs sb = carve_sorted(ws, n, m);
+    if (!ws.ok()) {
+        set_error("workspace too small for the bound sweep");
+        return SDFI_ERR_WORKSPACE;
+    }
+    // extent, band, and the Morton orders of samples and queries
+    extent_partial_kernel<<<EXT_BLOCKS, 256, 0, st>>>(samples, n, queries, m, sb.parts);
+    extent_final_kernel<<<1, 64, 0, st>>>(sb.parts, EXT_BLOCKS, opt.tie_tol, sb.ext);
+    morton_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(samples, 4, n, sb.ext, sb.keys_in, sb.idx_in);
+    SDFI_HIP(hipcub::DeviceRadixSort::SortPairs(sb.cub, sb.cub_bytes, sb.keys_in, sb.keys_out, sb.idx_in, sb.sperm,
+                                                (int)n, 0, 30, st));
+    pack_sorted_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(samples, sb.sperm, n, sb.ps);
+    tile_box_kernel<<<(unsigned)((n + TILE - 1) / TILE), TILE, 0, st>>>(sb.ps, n, sb.tbox);
+    morton_kernel<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(queries, 3, m, sb.ext, sb.keys_in, sb.idx_in);
+    SDFI_HIP(hipcub::DeviceRadixSort::SortPairs(sb.cub, sb.cub_bytes, sb.keys_in, sb.keys_out, sb.idx_in, sb.qperm,
+                                                (int)m, 0, 30, st));
+    SDFI_HIP(hipGetLastError());
+    SDFI_HIP(hipMemsetAsync(b.overflows, 0, sizeof(int64_t), st));
+    KernelTimer t1("sweep", st);
+    sweep_sorted_kernel<<<(unsigned)((m + MQ - 1) / MQ), MQ, 0, st>>>(sb.ps, (int)n, sb.tbox, queries, sb.qperm, m,
+                                                                       sb.ext, b.o);
+    t1.stop();
+    SDFI_HIP(hipGetLastError());
+    KernelTimer t2("resolve", st);
+    resolve_kernel<float><<<(unsigned)((m + 3) / 4), 256, 0, st>>>(samples, n, queries, m, 0.0f, b.o, opt.tol,
+                                                                    opt.tie_tol, lo, hi, argmax, argmin, flags,
+                                                                    b.overflows, sb.sperm, &sb.ext->eps);
     t2.stop();
     SDFI_HIP(hipGetLastError());
     if (overflow_count) {
@@ -352,10 +778,12 @@ static double eps_f64(const sdfi_options &o) { return o.tie_tol * 1.001 + 1e-15;
 
 size_t bounds_ws(int64_t n, int64_t m, const sdfi_options &o) {
     Carver c(nullptr, 0, true);
-    if (o.precision == SDFI_PREC_FP32_FP64_RECHECK)
+    if (o.precision == SDFI_PREC_FP32_FP64_RECHECK) {
         carve_sweep<float>(c, n, m);
-    else
+        carve_sorted(c, n, m);
+    } else {
         carve_sweep<double>(c, n, m);
+    }
     return c.used + 256;
 }
 
@@ -364,8 +792,7 @@ sdfi_status run_bounds(const double *samples, int64_t n, const double *queries, 
                        const sdfi_options &o, hipStream_t st, int64_t *overflow_count) {
     if (m == 0) return SDFI_OK;
     if (o.precision == SDFI_PREC_FP32_FP64_RECHECK)
-        return launch<float, 4>(samples, n, queries, m, lo, hi, argmax, argmin, flags, ws, o, st,
-                                (float)eps_f32(o), overflow_count);
+        return launch_sorted(samples, n, queries, m, lo, hi, argmax, argmin, flags, ws, o, st, overflow_count);
     return launch<double, 2>(samples, n, queries, m, lo, hi, argmax, argmin, flags, ws, o, st, eps_f64(o),
                              overflow_count);
 }

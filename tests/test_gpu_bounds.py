@@ -56,6 +56,24 @@ def test_bounds_full_parity(prec, case):
     check_full(P, S, Q, prec)
 
 
+@pytest.mark.parametrize("case", ["cluster", "wide"])
+def test_bounds_matrix_path(case):
+    """Dense query clusters: most sample tiles are far from each 256-query
+    block and go through the matrix-core distances, the rest (and queries
+    coinciding with samples) through the direct formula."""
+    rng = np.random.default_rng(17)
+    from sdfgen import shapes
+    if case == "cluster":
+        P = configs.grid_centres(30)
+        Q = np.vstack([rng.uniform(0.4, 0.6, (20000, 3)), P[rng.choice(len(P), 64, replace=False)]])
+    else:   # coordinates over [-1, 1]^3, queries near the middle
+        P = rng.uniform(-1.0, 1.0, (20000, 3))
+        Q = np.vstack([rng.uniform(-0.2, 0.2, (15000, 3)), P[:50]])
+    S = shapes.sphere_sdf(P, (0.45, 0.5, 0.55), 0.3)
+    print(f"bounds matrix path {case} n={len(S)} m={len(Q)}", flush=True)
+    check_full(P, S, Q, "fp32")
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_bounds_sphere16_full(prec):
     w = configs.sphere(16)
