@@ -91,6 +91,31 @@ __device__ int64_t threatened(const GInst &I, int64_t N, const double *q, double
     return cnt > n + m ? n + m : cnt;
 }
 
+// First guess for a threatened sphere (o, r) whose witness W lies inside the
+// new ball (q, R): the point just outside that ball's cap on the sphere,
+// nearest to W (the old uncovered region most likely straddles the cap's
+// rim there).  Only orders the search.
+__device__ inline void rim_hint(const double *o, double r, const double *q, double R, const double *W, double *h) {
+    for (int j = 0; j < 3; ++j) h[j] = W[j];
+    double u[3] = {q[0] - o[0], q[1] - o[1], q[2] - o[2]};
+    const double D = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    if (!(D > 0.0) || !(R > 0.0) || !(r > 0.0)) return;
+    for (int j = 0; j < 3; ++j) u[j] /= D;
+    const double c0 = (r * r + D * D - R * R) / (2.0 * r * D);
+    if (!(c0 > -1.0 && c0 < 1.0)) return;
+    double w[3] = {(W[0] - o[0]) / r, (W[1] - o[1]) / r, (W[2] - o[2]) / r};
+    const double wu = w[0] * u[0] + w[1] * u[1] + w[2] * u[2];
+    double t[3] = {w[0] - wu * u[0], w[1] - wu * u[1], w[2] - wu * u[2]};
+    double tn = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    if (!(tn > 1e-12)) {  // W on the axis: any direction across it
+        geom::basis(u, t, w);
+        tn = 1.0;
+    }
+    const double c1 = c0 - 1e-7 * sqrt(1.0 - c0 * c0);  // just outside the cap
+    const double r1 = sqrt(fmax(0.0, 1.0 - c1 * c1));
+    for (int j = 0; j < 3; ++j) h[j] = o[j] + r * (c1 * u[j] + r1 * t[j] / tn);
+}
+
 // Exact re-search of the threatened spheres with the ball (q, s) added, waves
 // in parallel; results into I.pend.  SH.fail = 1 if some sphere has no
 // uncovered point left (with `keep_going` the search continues and such
@@ -127,8 +152,9 @@ __device__ void revalidate(const GInst &I, int64_t N, const double *q, double s,
             int64_t c = I.list[t];
             B.skip = c;
             const double *p = I.CP + 4 * c;
-            double x[3];
-            int st = geom::lazy_exist(B, p, fabs(p[3]), I.CW + 3 * c, SH.kp[w], SH.kid[w], I.flist + (int64_t)w * I.fcap, I.fcap, x);
+            double x[3], hint[3];
+            rim_hint(p, fabs(p[3]), q, fabs(s) - tol, I.CW + 3 * c, hint);
+            int st = geom::lazy_exist(B, p, fabs(p[3]), hint, SH.kp[w], SH.kid[w], I.flist + (int64_t)w * I.fcap, I.fcap, x);
             if (ln == 0) {
                 atomicAdd(&I.counts[C_SEARCH], 1ull);
                 if (st == geom::ST_NUMERIC) atomicAdd(&I.counts[C_NUMERIC], 1ull);
