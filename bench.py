@@ -1,6 +1,7 @@
 """Benchmark of the hot path on one MI355X.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-greedy] [--no-batched]
+                [--copy-bytes N]
 
 Timed step (the JSON line's `value`): the dense query x sample bound
 reduction (Sec. 4.3 cone bounds with argmin/argmax, float32 sweep and float64
@@ -21,12 +22,21 @@ around it (wall clock):
             balls64 queries on one host core.
 Each leg prints a progress line on stderr when it ends.  Prints one JSON
 line on stdout.
+
+roofline.traffic is the sweep kernel's HBM bytes per launch from the
+FETCH_SIZE and WRITE_SIZE counter runs recorded in
+profiles/sweep_traffic_balls64.md, reported only while the sweep's source
+is the one those counters were taken on (null otherwise).  --copy-bytes N
+adds one plain device copy of N bytes after the timed steps: the
+calibration kernel of those counter runs.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -41,6 +51,25 @@ FLOP_PER_PAIR = 13
 FP32_VECTOR_PEAK = 157.3e12  # MI355X published float32 vector peak, FLOP/s
 BATCH_COUNT = 64
 BATCH_GRIDS = (4, 5, 6)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic_balls64.md")
+SWEEP_SOURCE = os.path.join(ROOT, "paper_2605_01919_amd", "csrc", "bounds.hip")
+
+
+def recorded_traffic():
+    """HBM bytes per sweep launch from the recorded counter runs, or None when
+    the sweep's source changed since they were taken."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+        src = hashlib.sha256(open(SWEEP_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    sha = re.search(r"bounds\.hip sha256: ([0-9a-f]{64})", text)
+    val = re.search(r"traffic_bytes_per_launch: ([0-9]+)", text)
+    if not sha or not val or sha.group(1) != src:
+        return None
+    return int(val.group(1))
 
 
 def progress(msg):
@@ -91,6 +120,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-greedy", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the hot path runs on a "
@@ -123,6 +153,14 @@ def main():
     pairs = n * m
     achieved = FLOP_PER_PAIR * pairs / (sweep_ms * 1e-3)
     progress(f"bounds balls64: {ms:.2f} ms/step, sweep kernel {sweep_ms:.2f} ms, resolve {resolve_ms:.2f} ms")
+    if args.copy_bytes > 0:
+        src_buf = torch.ones(args.copy_bytes, dtype=torch.uint8, device=dev)
+        dst_buf = torch.empty_like(src_buf)
+        torch.cuda.synchronize()
+        dst_buf.copy_(src_buf)
+        torch.cuda.synchronize()
+        progress(f"plain copy of {args.copy_bytes} bytes done")
+        del src_buf, dst_buf
     out = {
         "metric": "G query-sample bound evals/s + queries/s, batched vs plain, at 1e-5 abs",
         "value": round(pairs / (ms * 1e-3) / 1e9, 2), "unit": "G pair-evals/s",
@@ -133,8 +171,8 @@ def main():
                    "samples": n, "queries": m, "pairs": pairs,
                    "step": "sdfi_bounds: float32 sweep + float64 tie resolution"},
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 2), "peak": FP32_VECTOR_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK, 4), "traffic": None,
-                     "kernel": "sweep_kernel", "kernel_ms": round(sweep_ms, 3),
+                     "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK, 4), "traffic": recorded_traffic(),
+                     "kernel": "sweep_sorted_kernel", "kernel_ms": round(sweep_ms, 3),
                      "flop_per_launch": FLOP_PER_PAIR * pairs},
     }
     if not args.no_greedy:

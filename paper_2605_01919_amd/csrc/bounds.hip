@@ -103,6 +103,36 @@ __device__ inline void note_tile(int side, int64_t qi, int tile, T tv, T &run, u
     ++cnt;
 }
 
+// note_tile on a work-group's lists kept in LDS: entry e of side `side` of
+// local query `lq` at [side][e][lq]
+__device__ inline void note_tile_lds(int side, int lq, int tile, float tv, float &run, uint32_t &cnt, float eps,
+                                     int32_t (*lt)[LIST][256], float (*lv)[LIST][256]) {
+    bool near = side == 0 ? (tv >= run - eps) : (tv <= run + eps);
+    if (!near) return;
+    if (side == 0 ? tv > run : tv < run) run = tv;
+    if (cnt & OVERFLOW_BIT) return;
+    if (cnt == LIST) {
+        uint32_t k = 0;
+        for (uint32_t e = 0; e < LIST; ++e) {
+            const float v = lv[side][e][lq];
+            const bool keep = side == 0 ? (v >= run - eps) : (v <= run + eps);
+            if (keep) {
+                lv[side][k][lq] = v;
+                lt[side][k][lq] = lt[side][e][lq];
+                ++k;
+            }
+        }
+        cnt = k;
+        if (cnt == LIST) {
+            cnt = OVERFLOW_BIT;
+            return;
+        }
+    }
+    lt[side][cnt][lq] = tile;
+    lv[side][cnt][lq] = tv;
+    ++cnt;
+}
+
 template <typename T, int QPT>
 __global__ __launch_bounds__(BT) void sweep_kernel(const Pt4<T> *__restrict__ samples, int n,
                                                    const double *__restrict__ queries, int64_t m, T eps,
@@ -220,20 +250,22 @@ __global__ __launch_bounds__(256) void resolve_kernel(const double *__restrict__
                                                       SweepOut<T> o, double tol, double tie, double *lo_out,
                                                       double *hi_out, int32_t *argmax, int32_t *argmin,
                                                       uint32_t *flags, int64_t *overflows,
-                                                      const int32_t *__restrict__ sperm, const float *eps_dev) {
+                                                      const int32_t *__restrict__ sperm, const float *eps_dev,
+                                                      const int32_t *__restrict__ qinv) {
     const int lane = threadIdx.x & 63;
     const int64_t qi = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
     if (qi >= m) return;
     if (eps_dev) eps = (T)*eps_dev;
+    const int64_t li = qinv ? (int64_t)qinv[qi] : qi;  // slot of this query's lists
     const double q[3] = {queries[3 * qi], queries[3 * qi + 1], queries[3 * qi + 2]};
     double ext[2];
     int64_t arg[2];
     int tied[2];
     for (int side = 0; side < 2; ++side) {
-        uint32_t cnt = o.count[2 * qi + side];
+        uint32_t cnt = o.count[2 * li + side];
         const bool full = (cnt & OVERFLOW_BIT) != 0;
-        const T run = o.run[2 * qi + side];
-        const int64_t lb = (qi * 2 + side) * LIST;
+        const T run = o.run[2 * li + side];
+        const int64_t lb = (li * 2 + side) * LIST;
         const int nt = full ? (int)((n + TILE - 1) / TILE) : (int)cnt;
         // exact extreme over the candidate tiles
         double best = side == 0 ? -INFINITY : INFINITY;
@@ -311,6 +343,7 @@ __global__ __launch_bounds__(256) void resolve_kernel(const double *__restrict__
 // ---- float32 sweep over spatially sorted data ----
 
 constexpr int MQ = 256;             // queries per work-group of the sorted sweep (4 wavefronts x 64)
+static_assert(MQ == 256, "the LDS candidate lists are laid out for 256 queries");
 constexpr int EXT_BLOCKS = 256;     // partial reductions of the extent
 constexpr float U32 = 5.9604645e-8f;  // unit roundoff of float32
 
@@ -486,10 +519,15 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
                                                           const double *__restrict__ queries,
                                                           const int32_t *__restrict__ qperm, int64_t m,
                                                           const Extent *__restrict__ ext, SweepOut<float> o) {
-    __shared__ float4 raw[TILE];  // tile samples (x, y, z, s)
-    __shared__ float4 cen[TILE];  // (-2 a, |a|^2) with a = p - c
-    __shared__ float sv[TILE];    // tile values
+    // a tile is either near (raw samples (x, y, z, s)) or far ((-2 a, |a|^2) with
+    // a = p - c, values apart): the two layouts share one LDS array
+    __shared__ float4 tilebuf[TILE];
+    __shared__ float sv[TILE];    // tile values (far tiles)
+    float4 *const raw = tilebuf;
+    float4 *const cen = tilebuf;
     __shared__ float wbox[MQ / 64][6];
+    __shared__ int32_t ltile[2][LIST][MQ];  // candidate lists of the work-group's queries
+    __shared__ float lval[2][LIST][MQ];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t sq = (int64_t)blockIdx.x * MQ + tid;
     const bool valid = sq < m;
@@ -547,11 +585,12 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
             __syncthreads();
             if (tid < cnt) {
                 const float4 p = ps[(int64_t)t * TILE + tid];
-                raw[tid] = p;
                 if (far) {
                     const float ax = p.x - cx, ay = p.y - cy, az = p.z - cz;
                     cen[tid] = make_float4(-2.0f * ax, -2.0f * ay, -2.0f * az, ax * ax + ay * ay + az * az);
                     sv[tid] = p.w;
+                } else {
+                    raw[tid] = p;
                 }
             }
             __syncthreads();
@@ -626,18 +665,38 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
                     thi = fminf(thi, p.w + d);
                 }
             }
-            if (valid) {
-                note_tile<float>(0, qi, t, tlo, run_lo, clo, eps, o);
-                note_tile<float>(1, qi, t, thi, run_hi, chi, eps, o);
-            }
+            note_tile_lds(0, tid, t, tlo, run_lo, clo, eps, ltile, lval);
+            note_tile_lds(1, tid, t, thi, run_hi, chi, eps, ltile, lval);
         }
     }
+    // lists and extremes leave in sorted order (slot sq), contiguous per work-group
     if (valid) {
-        o.run[2 * qi] = run_lo;
-        o.run[2 * qi + 1] = run_hi;
-        o.count[2 * qi] = clo;
-        o.count[2 * qi + 1] = chi;
+        o.run[2 * sq] = run_lo;
+        o.run[2 * sq + 1] = run_hi;
+        for (int side = 0; side < 2; ++side) {
+            const uint32_t c = side == 0 ? clo : chi;
+            const float run = side == 0 ? run_lo : run_hi;
+            // entries noted before the extreme settled may have left its band: drop them
+            uint32_t k = 0;
+            if (!(c & OVERFLOW_BIT)) {
+                for (uint32_t e = 0; e < c; ++e) {
+                    const float v = lval[side][e][tid];
+                    if (side == 0 ? (v >= run - eps) : (v <= run + eps)) {
+                        o.tiles[(sq * 2 + side) * LIST + k] = ltile[side][e][tid];
+                        o.vals[(sq * 2 + side) * LIST + k] = v;
+                        ++k;
+                    }
+                }
+            }
+            o.count[2 * sq + side] = (c & OVERFLOW_BIT) ? c : k;
+        }
     }
+}
+
+// qinv[qperm[k]] = k
+__global__ void invert_kernel(const int32_t *__restrict__ perm, int64_t k, int32_t *__restrict__ inv) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < k) inv[perm[i]] = (int32_t)i;
 }
 
 // workspace of the sorted float32 path
@@ -645,7 +704,7 @@ struct SortedBufs {
     ExtPart *parts;
     Extent *ext;
     uint32_t *keys_in, *keys_out;
-    int32_t *idx_in, *sperm, *qperm;
+    int32_t *idx_in, *sperm, *qperm, *qinv;
     float4 *ps, *tbox;
     void *cub;
     size_t cub_bytes;
@@ -668,6 +727,7 @@ SortedBufs carve_sorted(Carver &c, int64_t n, int64_t m) {
     b.idx_in = c.take<int32_t>(k);
     b.sperm = c.take<int32_t>(n);
     b.qperm = c.take<int32_t>(m);
+    b.qinv = c.take<int32_t>(m);
     b.ps = c.take<float4>(n);
     b.tbox = c.take<float4>(2 * ((n + TILE - 1) / TILE));
     b.cub_bytes = std::max(cub_sort_bytes(n), cub_sort_bytes(m));
@@ -719,7 +779,7 @@ sdfi_status launch(const double *samples, int64_t n, const double *queries, int6
     KernelTimer t2("resolve", st);
     resolve_kernel<T><<<(unsigned)((m + 3) / 4), 256, 0, st>>>(samples, n, queries, m, eps, b.o, opt.tol,
                                                                 opt.tie_tol, lo, hi, argmax, argmin, flags,
-                                                                b.overflows, nullptr, nullptr);
+                                                                b.overflows, nullptr, nullptr, nullptr);
     t2.stop();
     SDFI_HIP(hipGetLastError());
     if (overflow_count) {
@@ -748,6 +808,7 @@ sdfi_status launch_sorted(const double *samples, int64_t n, const double *querie
     morton_kernel<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(queries, 3, m, sb.ext, sb.keys_in, sb.idx_in);
     SDFI_HIP(hipcub::DeviceRadixSort::SortPairs(sb.cub, sb.cub_bytes, sb.keys_in, sb.keys_out, sb.idx_in, sb.qperm,
                                                 (int)m, 0, 30, st));
+    invert_kernel<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(sb.qperm, m, sb.qinv);
     SDFI_HIP(hipGetLastError());
     SDFI_HIP(hipMemsetAsync(b.overflows, 0, sizeof(int64_t), st));
     KernelTimer t1("sweep", st);
@@ -758,7 +819,7 @@ sdfi_status launch_sorted(const double *samples, int64_t n, const double *querie
     KernelTimer t2("resolve", st);
     resolve_kernel<float><<<(unsigned)((m + 3) / 4), 256, 0, st>>>(samples, n, queries, m, 0.0f, b.o, opt.tol,
                                                                     opt.tie_tol, lo, hi, argmax, argmin, flags,
-                                                                    b.overflows, sb.sperm, &sb.ext->eps);
+                                                                    b.overflows, sb.sperm, &sb.ext->eps, sb.qinv);
     t2.stop();
     SDFI_HIP(hipGetLastError());
     if (overflow_count) {
