@@ -147,7 +147,8 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
         if (fabs(p[3]) - geom::dist3(q, p) == depth) deepest = deepest < c ? deepest : c;
     }
     deepest = bmin_i64(deepest, S);
-    double bound = isinf(wbest) ? INFINITY : wbest * (1.0 + 1e-12) + 1e-15;
+    const double wbound = isinf(wbest) ? INFINITY : wbest * (1.0 + 1e-12) + 1e-15;
+    double bound = wbound, rbound = INFINITY;
     // A second upper bound: the exit of the ray from q away from the deepest
     // centre.  At each point of the ray, jump to the farthest exit among the
     // balls (shrunk by tie) holding it; the first point no ball holds is off
@@ -179,14 +180,22 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
             }
             step = bmax(step, S);
             if (!(step > 0.0)) {
-                bound = fmin(bound, t * (1.0 + 1e-12) + 1e-12);
+                rbound = t * (1.0 + 1e-12) + 1e-12;
+                bound = fmin(bound, rbound);
                 break;
             }
             t += step + 1e-12;  // strictly past the exit of the ball left behind
         }
     }
     int64_t *lset = list + (N + 1);
-    for (int pass = 0; pass < 2; ++pass) {
+    // Both bounds can fall just short of the answer: a cached witness is only
+    // uncovered w.r.t. the tol-shrunk balls, and the ray may leave the sigma
+    // union inside a tol-thin overlap with an opposite-sign ball, whose
+    // uncovered edge lies within sqrt(2 R tol) of it.  A pass that finds
+    // nothing within its bound moves on to the larger bound plus that margin,
+    // then to no bound at all; what a pass finds within its bound is exact.
+    const double looser = fmax(isinf(wbound) ? 0.0 : wbound, isinf(rbound) ? 0.0 : rbound) + 4e-3;
+    for (int pass = 0; pass < 3; ++pass) {
         // candidate spheres: sigma spheres passing within `bound` of q (deepest first)
         int64_t len = 0, nl = 0;
         for (int64_t base = 0; base < N; base += BS) {
@@ -297,7 +306,7 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
         if (numeric) return -2;
         if (res > 0) return res;
         if (isinf(bound)) break;
-        bound = INFINITY;  // the witness bound was not beaten: search without it
+        bound = (pass == 0 && looser > bound && !(isinf(wbound) && isinf(rbound))) ? looser : INFINITY;
     }
     return -1;
 }
