@@ -147,6 +147,7 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
         if (fabs(p[3]) - geom::dist3(q, p) == depth) deepest = deepest < c ? deepest : c;
     }
     deepest = bmin_i64(deepest, S);
+    if (deepest == INT64_MAX) return -2;  // no ball attains the depth (only with NaN data): no answer
     const double wbound = isinf(wbest) ? INFINITY : wbest * (1.0 + 1e-12) + 1e-15;
     double bound = wbound, rbound = INFINITY;
     // A second upper bound: the exit of the ray from q away from the deepest
@@ -237,39 +238,58 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
         double wlow = INFINITY;
         geom::Holders hold;  // balls that held whole search regions (this pass's local numbering)
         const int w = wid();
+        // each wave takes PULL candidates at a time: lanes load them and their
+        // lower bounds together, then the survivors are searched in list order
+        // (re-pruned against the bound as it shrinks)
+        constexpr int PULL = 16;
         for (int guard = 0; guard < (1 << 30); ++guard) {
-            int k = 0;
-            if (lane() == 0) k = atomicAdd(&S.counter, 1);
-            k = __shfl(k, 0, 64);
-            if (k >= len) break;
-            int64_t i = list[k];
-            const double *p = p4 + 4 * i;
-            double lbi = fabs(geom::dist3(q, p) - fabs(p[3]));
-            unsigned long long cb = 0;
-            if (lane() == 0) cb = __hip_atomic_load(&S.bound_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            double cur = __longlong_as_double((long long)__shfl(cb, 0, 64));  // wave-uniform
-            // prune only clearly worse spheres: exact ties must reach the tie-break
-            if (lbi > cur * (1.0 + 1e-12) + 1e-15) continue;
-            double d, x[3];
-            int kk = geom::lazy_nearest(L, p, fabs(p[3]), q, cur * (1.0 + 1e-12) + 1e-15, kp[w], kid[w], flist + (int64_t)w * fcap, fcap, &d, x, &hold);
-            if (kk < 0) {
-                // a capped search proved only that this sphere has no uncovered
-                // point nearer than d (a lower bound); it matters only if the
-                // final answer is farther than that
-                wlow = fmin(wlow, d);
-                continue;
+            int k0 = 0;
+            if (lane() == 0) k0 = atomicAdd(&S.counter, PULL);
+            k0 = __shfl(k0, 0, 64);
+            if (k0 >= len) break;
+            const int64_t kl = (int64_t)k0 + lane();
+            const bool have = lane() < PULL && kl < len;
+            const int64_t myi = have ? list[kl] : 0;
+            double mylb = INFINITY;
+            if (have) {
+                const double *pp = p4 + 4 * myi;
+                mylb = fabs(geom::dist3(q, pp) - fabs(pp[3]));
             }
-            if (kk && better(d, i != deepest, lbi, i, wd, wnd, wlb, wi)) {
-                wd = d;
-                wnd = i != deepest;
-                wlb = lbi;
-                wi = i;
-                wk = kk;
-                wx[0] = x[0];
-                wx[1] = x[1];
-                wx[2] = x[2];
-                if (lane() == 0)
-                    atomicMin(&S.bound_bits, (unsigned long long)__double_as_longlong(d));
+            unsigned long long pending = __ballot(have);
+            while (pending) {
+                unsigned long long cb = 0;
+                if (lane() == 0) cb = __hip_atomic_load(&S.bound_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                const double cur = __longlong_as_double((long long)__shfl(cb, 0, 64));  // wave-uniform
+                // prune only clearly worse spheres: exact ties must reach the tie-break
+                pending &= __ballot(!(mylb > cur * (1.0 + 1e-12) + 1e-15));
+                if (!pending) break;
+                const int src = __ffsll((long long)pending) - 1;
+                pending &= pending - 1ull;
+                const int64_t i = __shfl(myi, src, 64);
+                const double lbi = __shfl(mylb, src, 64);
+                const double *p = p4 + 4 * i;
+                double d, x[3];
+                int kk = geom::lazy_nearest(L, p, fabs(p[3]), q, cur * (1.0 + 1e-12) + 1e-15, kp[w], kid[w],
+                                            flist + (int64_t)w * fcap, fcap, &d, x, &hold);
+                if (kk < 0) {
+                    // a capped search proved only that this sphere has no uncovered
+                    // point nearer than d (a lower bound); it matters only if the
+                    // final answer is farther than that
+                    wlow = fmin(wlow, d);
+                    continue;
+                }
+                if (kk && better(d, i != deepest, lbi, i, wd, wnd, wlb, wi)) {
+                    wd = d;
+                    wnd = i != deepest;
+                    wlb = lbi;
+                    wi = i;
+                    wk = kk;
+                    wx[0] = x[0];
+                    wx[1] = x[1];
+                    wx[2] = x[2];
+                    if (lane() == 0)
+                        atomicMin(&S.bound_bits, (unsigned long long)__double_as_longlong(d));
+                }
             }
         }
         if (lane() == 0) {

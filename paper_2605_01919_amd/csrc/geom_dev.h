@@ -714,6 +714,10 @@ __device__ inline int lazy_nearest(const Balls &B0, const double *o, double r, c
         // the lowest rim index with the best distance
         const int64_t cand = (cd == best && ckind) ? ((int64_t)crim << 8) + lane : INT64_MAX;
         const int64_t pick = wmin_i64(cand);
+        if (pick == INT64_MAX) {  // no lane holds the best distance (NaN geometry): no answer
+            *dist_out = lowest;
+            return -1;
+        }
         const int src = (int)(pick & 255);
         const int srim = (int)(pick >> 8);
         double v[3] = {0.0, 0.0, 0.0};
