@@ -54,20 +54,21 @@ struct Cap {
 // only balls with |lq - p| < |s| + lb take part (a local set: balls that can
 // cover a point within lb of lq).
 struct Balls {
-    const double *p4;
-    int64_t N;
-    double extra[4];
-    int has_extra;
-    double tol;
-    int64_t skip;
-    double lq[3];
-    double lb;
-    const int64_t *idx;  // optional: the balls are rows idx[0..N) of p4 instead of [0, N)
+    const double *p4 = nullptr;
+    int64_t N = 0;
+    double extra[4] = {0.0, 0.0, 0.0, 0.0};
+    int has_extra = 0;
+    double tol = 0.0;
+    int64_t skip = -1;
+    double lq[3] = {0.0, 0.0, 0.0};
+    double lb = INFINITY;
+    const int64_t *idx = nullptr;    // optional: the balls are rows idx[0..N) of p4 instead of [0, N)
+    const int32_t *idx32 = nullptr;  // the same with 32-bit row indices (a search's own compacted list)
     // optional region of interest on the searched sphere, the cap {v : v.ru >= rc}
     // (rs = sqrt(1 - rc^2)); caps that cannot meet it are ignored.  Exact for
     // every question asked about points of the region.
-    int use_region;
-    double ru[3], rc, rs;
+    int use_region = 0;
+    double ru[3] = {0.0, 0.0, 0.0}, rc = -1.0, rs = 0.0;
 };
 
 __device__ inline double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
@@ -78,9 +79,12 @@ __device__ inline double dist3(const double *a, const double *b) {
     return sqrt(dx * dx + dy * dy + dz * dz);
 }
 
+__device__ inline int64_t ball_row(const Balls &B, int64_t f) {
+    return B.idx32 ? (int64_t)B.idx32[f] : (B.idx ? B.idx[f] : f);
+}
 __device__ inline const double *ball_ptr(const Balls &B, int64_t f) {
     if (f >= B.N) return B.extra;
-    return B.p4 + 4 * (B.idx ? B.idx[f] : f);
+    return B.p4 + 4 * ball_row(B, f);
 }
 __device__ inline int64_t ball_count(const Balls &B) { return B.N + (B.has_extra ? 1 : 0); }
 
@@ -201,7 +205,7 @@ struct ListCaps {
     const int32_t *cl;  // ball indices of B with a cap on the sphere
     int cnt;
     __device__ int64_t count() const { return cnt; }
-    __device__ bool get(int64_t f, Cap &c) const { return cap_of(*B, cl[f], o, r, c) == 1; }
+    __device__ bool get(int64_t f, Cap &c) const { return cap_of(*B, cl ? (int64_t)cl[f] : f, o, r, c) == 1; }
 };
 
 // Walk rim R over the caps of `src` (skipping index `self`) from P0 in
@@ -415,12 +419,73 @@ __device__ inline int wave_list_caps(const Balls &B, const double *o, double r, 
     return cnt;
 }
 
+// wave_cover at v together with the list of the balls that have a cap on the
+// sphere: their rows of B.p4 in index order into cl (ccap entries; the extra
+// ball is reported apart).  *cnt: listed rows (may exceed ccap); *ecap: the
+// extra ball has a cap; *argpos: the position of *arg in the list (*cnt for
+// the extra ball).  A ball meets the sphere iff |r - R| < D < r + R; the
+// squared test only skips balls clearly apart, cap_of decides the rest.
+__device__ inline void wave_cover_list(const Balls &B, const double *o, double r, const double *v, double *mx,
+                                       int64_t *arg, int *whole, int32_t *cl, int ccap, int *cnt_out, int *ecap,
+                                       int64_t *argpos) {
+    const int lane = threadIdx.x & 63;
+    double best = -INFINITY;
+    int64_t bi = INT64_MAX, bp = INT64_MAX;
+    int wh = 0, ec = 0, cnt = 0;
+    const int64_t n = ball_count(B);
+    for (int64_t f0 = 0; f0 < n; f0 += 64) {
+        const int64_t f = f0 + lane;
+        int take = 0;
+        double m = -INFINITY;
+        if (f < n && f != B.skip) {
+            const double *p = ball_ptr(B, f);
+            const double R = fabs(p[3]) - B.tol;
+            const double dx = p[0] - o[0], dy = p[1] - o[1], dz = p[2] - o[2];
+            const double D2 = dx * dx + dy * dy + dz * dz;
+            const bool apart = !(R > 0.0) || D2 > (r + R) * (r + R) * (1.0 + 1e-12) + 1e-300 ||
+                               (R < r && D2 < (r - R) * (r - R) * (1.0 - 1e-12));
+            if (!apart) {
+                Cap cp;
+                const int st = cap_of(B, f, o, r, cp);
+                if (st == 2) wh = 1;
+                if (st == 1) {
+                    m = dot3(v, cp.u) - cp.c;
+                    if (f < B.N) take = 1;
+                    else ec = 1;
+                }
+            }
+        }
+        const unsigned long long bal = __ballot(take);
+        const int pos = cnt + (int)__popcll(bal & ((1ull << lane) - 1ull));
+        if (take && pos < ccap) cl[pos] = (int32_t)ball_row(B, f);
+        if (m > best) {
+            best = m;
+            bi = f;
+            bp = f < B.N ? pos : -1;  // -1: the extra ball, placed after the rows
+        }
+        cnt += (int)__popcll(bal);
+    }
+    __threadfence_block();
+    wave_sync_lds();
+    const double g = wmax(best);
+    const int64_t cand = (best == g) ? bi : INT64_MAX;
+    *mx = g;
+    *arg = wmin_i64(cand);
+    const int64_t pc = (best == g && bi == *arg) ? bp : INT64_MAX;
+    const int64_t ap = wmin_i64(pc == -1 ? (int64_t)cnt : pc);
+    *argpos = ap;
+    *whole = wor(wh);
+    *ecap = wor(ec);
+    *cnt_out = cnt;
+}
+
 // Exact: does sphere (o, r) have a point no ball covers?  Writes one (nudged
 // off the rim it was found on) to x.  kp: this wave's LDS scratch (KMAX caps),
 // kid: their ball indices.  hint orders the search only.
-__device__ inline int lazy_exist(const Balls &B, const double *o, double r, const double *hint, Cap *kp,
+__device__ inline int lazy_exist(const Balls &B0, const double *o, double r, const double *hint, Cap *kp,
                                  int64_t *kid, int32_t *cl, int ccap, double *x) {
     const int lane = threadIdx.x & 63;
+    Balls B = B0;
     if (!(r > 0.0)) {
         // a sphere of radius 0 is its centre: covered iff |o - p| < |s| - tol for some ball
         double best = -INFINITY;
@@ -450,11 +515,27 @@ __device__ inline int lazy_exist(const Balls &B, const double *o, double r, cons
     double mx;
     int64_t arg;
     int whole;
-    wave_cover(B, o, r, vh, -1, &mx, &arg, &whole);
+    // the first test also lists the balls that meet the sphere; when they fit
+    // in cl the rest of the search runs over that list only
+    int ncl = 0, ecap = 0;
+    int64_t argpos = 0;
+    wave_cover_list(B, o, r, vh, &mx, &arg, &whole, cl, ccap, &ncl, &ecap, &argpos);
     if (whole) return ST_NONE;
     if (!(mx > COVER_EPS)) {
         for (int j = 0; j < 3; ++j) x[j] = o[j] + r * vh[j];
         return ST_FOUND;
+    }
+    const bool compact = ncl <= ccap;
+    if (compact) {
+        Balls C = B;
+        C.N = ncl;
+        C.idx = nullptr;
+        C.idx32 = cl;
+        C.skip = -1;
+        C.lb = INFINITY;
+        C.has_extra = B.has_extra && ecap;
+        B = C;
+        arg = argpos;
     }
     int k = 0;
     if (lane == 0) {
@@ -545,15 +626,17 @@ __device__ inline int lazy_exist(const Balls &B, const double *o, double r, cons
     // listed caps.  Its cost grows with the cube of the cap count, so it is
     // bounded by the list's size ccap: beyond it the search reports a numeric
     // failure.
-    const int ncap = wave_list_caps(B, o, r, cl, ccap);
-    if (ncap > ccap) return ST_NUMERIC;
-    const ListCaps all{&B, o, r, cl, ncap};
+    // (after compaction every ball of B has a cap and B's own list stands in)
+    const int ncap = compact ? (int)ball_count(B) : wave_list_caps(B, o, r, cl, ccap);
+    if (!compact && ncap > ccap) return ST_NUMERIC;  // the list holds only the first ccap
+    const int32_t *lst = compact ? nullptr : cl;
+    const ListCaps all{&B, o, r, lst, ncap};
     for (int e0 = 0; e0 < ncap; e0 += 64) {
         const int e = e0 + lane;
         int64_t first = INT64_MAX;
         double fx[3] = {0.0, 0.0, 0.0};
         Cap ce;
-        if (e < ncap && cap_of(B, cl[e], o, r, ce) == 1) {
+        if (e < ncap && cap_of(B, lst ? (int64_t)lst[e] : (int64_t)e, o, r, ce) == 1) {
             Rim R;
             make_rim(ce, R);
             double px, py;
@@ -573,6 +656,13 @@ __device__ inline int lazy_exist(const Balls &B, const double *o, double r, cons
         }
     }
     return ST_NONE;
+}
+
+// lazy_exist kept out of line, for callers whose own code it would bloat (the
+// greedy's candidate check; a nearest search whose q is the sphere's centre)
+__device__ __noinline__ int lazy_exist_call(const Balls &B, const double *o, double r, const double *hint, Cap *kp,
+                                            int64_t *kid, int32_t *cl, int ccap, double *x) {
+    return lazy_exist(B, o, r, hint, kp, kid, cl, ccap, x);
 }
 
 // Recently seen balls that held a whole search region (ball indices, -1 empty).
@@ -615,7 +705,7 @@ __device__ inline int lazy_nearest(const Balls &B0, const double *o, double r, c
     int whole;
     if (!(gn > 0.0)) {
         if (r > bound) return 0;
-        int s = lazy_exist(B, o, r, nullptr, kp, kid, cl, ccap, x);
+        int s = lazy_exist_call(B, o, r, nullptr, kp, kid, cl, ccap, x);
         if (s == ST_NUMERIC) {
             *dist_out = r;
             return -1;

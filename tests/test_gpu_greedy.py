@@ -182,3 +182,29 @@ def test_batched_instance_matches_oracle():
     r = OG.greedy_interpolate(x.points, x.values, x.queries, order, W, stop=400, progress=100)
     head = order[:400]
     np.testing.assert_allclose(b["values"].cpu().numpy()[head], r.values[head], rtol=0, atol=1e-5)
+
+
+def test_greedy_sphere12_properties():
+    """A size the oracle's greedy cannot follow in seconds (1728 samples, 13824
+    queries): properties that hold at any size.  Prop. 1 through the
+    certificate, every query assigned, each value inside the cone bounds of
+    the samples (recomputed by the oracle for sampled queries), and the sign
+    forced inside a ball of either sign (Sec. 4.3)."""
+    from oracle import bounds as OB
+    w = configs.sphere(12)
+    print("greedy sphere12 full", flush=True)
+    out = sdfi.greedy(dev(np.c_[w.points, w.values]), dev(w.queries), grid=w.grid, certify=True)
+    rep = out["report"]
+    assert rep["n_violations_pairwise"] == 0 and rep["n_violations_witness"] == 0, rep
+    assert rep["n_unresolved"] == 0 and rep["n_infeasible"] == 0 and rep["n_search_capped"] == 0, rep
+    v = out["values"].cpu().numpy()
+    assert np.all(np.isfinite(v))
+    idx = np.random.default_rng(12).choice(w.m, 300, replace=False)
+    for j in idx:
+        lo, hi, _, _, _ = OB.bounds_one(w.queries[j], w.points, w.values)
+        assert lo - TOL <= v[j] <= hi + TOL, (j, lo, v[j], hi)
+        d = dist(w.points, w.queries[j])
+        if np.any(d < w.values - TOL):
+            assert v[j] > 0.0, j
+        if np.any(d < -w.values - TOL):
+            assert v[j] < 0.0, j
