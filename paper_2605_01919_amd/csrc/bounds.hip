@@ -242,6 +242,14 @@ __device__ inline int wave_sum(int v) {
 
 __device__ inline int sign_class(double s, double tie) { return s > tie ? 1 : (s < -tie ? -1 : 0); }
 
+// float32 value of one pair (the sweep's direct formula) within eps of the
+// float32 extreme `run` of its side
+__device__ inline bool near32(float4 p, const float *qf, int side, float run, float eps) {
+    const float dx = qf[0] - p.x, dy = qf[1] - p.y, dz = qf[2] - p.z;
+    const float d = __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz);
+    return side == 0 ? (p.w - d >= run - eps) : (p.w + d <= run + eps);
+}
+
 // sperm (nullable): tile t holds the samples sperm[t*TILE ...] (sorted order);
 // eps_dev (nullable): the band, computed on the device, replaces eps.
 template <typename T>
@@ -251,12 +259,17 @@ __global__ __launch_bounds__(256) void resolve_kernel(const double *__restrict__
                                                       double *hi_out, int32_t *argmax, int32_t *argmin,
                                                       uint32_t *flags, int64_t *overflows,
                                                       const int32_t *__restrict__ sperm, const float *eps_dev,
-                                                      const int32_t *__restrict__ qinv) {
+                                                      const int32_t *__restrict__ qinv,
+                                                      const float4 *__restrict__ ps32) {
     const int lane = threadIdx.x & 63;
     const int64_t qi = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
     if (qi >= m) return;
     if (eps_dev) eps = (T)*eps_dev;
     const int64_t li = qinv ? (int64_t)qinv[qi] : qi;  // slot of this query's lists
+    // with the float32 copy (sorted like the tiles), a listed tile's samples go
+    // to float64 only when their float32 value is within eps of the float32
+    // extreme: every sample within the tie band of the float64 extreme is
+    const float qf[3] = {(float)queries[3 * qi], (float)queries[3 * qi + 1], (float)queries[3 * qi + 2]};
     const double q[3] = {queries[3 * qi], queries[3 * qi + 1], queries[3 * qi + 2]};
     double ext[2];
     int64_t arg[2];
@@ -281,7 +294,7 @@ __global__ __launch_bounds__(256) void resolve_kernel(const double *__restrict__
             }
             for (int j = lane; j < TILE; j += 64) {
                 int64_t i = (int64_t)t * TILE + j;
-                if (i < n) {
+                if (i < n && (full || !ps32 || near32(ps32[i], qf, side, (float)run, (float)eps))) {
                     const int64_t oi = sperm ? (int64_t)sperm[i] : i;
                     double v = pair_val(samples + 4 * oi, q, side);
                     best = side == 0 ? fmax(best, v) : fmin(best, v);
@@ -304,7 +317,7 @@ __global__ __launch_bounds__(256) void resolve_kernel(const double *__restrict__
             }
             for (int j = lane; j < TILE; j += 64) {
                 int64_t i = (int64_t)t * TILE + j;
-                if (i < n) {
+                if (i < n && (full || !ps32 || near32(ps32[i], qf, side, (float)run, (float)eps))) {
                     const int64_t oi = sperm ? (int64_t)sperm[i] : i;
                     double v = pair_val(samples + 4 * oi, q, side);
                     bool in = side == 0 ? (v >= best - tie) : (v <= best + tie);
@@ -779,7 +792,7 @@ sdfi_status launch(const double *samples, int64_t n, const double *queries, int6
     KernelTimer t2("resolve", st);
     resolve_kernel<T><<<(unsigned)((m + 3) / 4), 256, 0, st>>>(samples, n, queries, m, eps, b.o, opt.tol,
                                                                 opt.tie_tol, lo, hi, argmax, argmin, flags,
-                                                                b.overflows, nullptr, nullptr, nullptr);
+                                                                b.overflows, nullptr, nullptr, nullptr, nullptr);
     t2.stop();
     SDFI_HIP(hipGetLastError());
     if (overflow_count) {
@@ -819,7 +832,7 @@ sdfi_status launch_sorted(const double *samples, int64_t n, const double *querie
     KernelTimer t2("resolve", st);
     resolve_kernel<float><<<(unsigned)((m + 3) / 4), 256, 0, st>>>(samples, n, queries, m, 0.0f, b.o, opt.tol,
                                                                     opt.tie_tol, lo, hi, argmax, argmin, flags,
-                                                                    b.overflows, sb.sperm, &sb.ext->eps, sb.qinv);
+                                                                    b.overflows, sb.sperm, &sb.ext->eps, sb.qinv, sb.ps);
     t2.stop();
     SDFI_HIP(hipGetLastError());
     if (overflow_count) {
