@@ -1,7 +1,7 @@
 """Benchmark of the hot path on one MI355X.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-greedy] [--no-batched]
-                [--copy-bytes N]
+                [--no-repair] [--copy-bytes N]
 
 Timed step (the JSON line's `value`): the dense query x sample bound
 reduction (Sec. 4.3 cone bounds with argmin/argmax, float32 sweep and float64
@@ -15,9 +15,13 @@ around it (wall clock):
             witnesses, sequential assignment with exact validity checks,
             Prop. 1 certificate) of "sphere16" (16^3 samples, 32^3 queries),
             float64 throughout, in queries/s;
+  backward  the gradient of the sphere16 values w.r.t. the samples;
   batched   64 sphere/box union instances on uneven grids in one launch
             (one work-group per instance) against the same 64 instances
             run one after another through the single-instance entry;
+  repair    the pseudo-SDF repair of a CSG field (witnesses of all samples,
+            removal of the fully covered ones, minimum valid radius of the
+            removed samples and of scattered extension queries);
   cpu_baseline  the oracle's bound definition on a bounded sample of
             balls64 queries on one host core.
 Each leg prints a progress line on stderr when it ends.  Prints one JSON
@@ -51,6 +55,8 @@ FLOP_PER_PAIR = 13
 FP32_VECTOR_PEAK = 157.3e12  # MI355X published float32 vector peak, FLOP/s
 BATCH_COUNT = 64
 BATCH_GRIDS = (4, 5, 6)
+REPAIR_GRID = 48
+REPAIR_QUERIES = 50000
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic_balls64.md")
@@ -120,6 +126,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-greedy", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-repair", action="store_true")
     ap.add_argument("--copy-bytes", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -183,6 +190,10 @@ def main():
         rep = g["report"]
         bad = rep["n_violations_pairwise"] + rep["n_violations_witness"]
         progress(f"greedy sphere16: {gt:.1f} s, {c1.m / gt:.0f} queries/s, violations {bad}")
+        # gradient of sum(values) w.r.t. the samples through the active parents (extension)
+        ones = torch.ones(c1.m, dtype=torch.float64, device=dev)
+        _, bt = wall(lambda: sdfi.greedy_backward(ones, s1, q1, g["values"], g["active"], g["kind"]))
+        progress(f"backward sphere16: {bt * 1e3:.2f} ms")
         out["greedy"] = {
             "workload": "sphere16: sphere SDF, 16^3 samples, 32^3 refinement queries, float64",
             "queries": c1.m, "samples": c1.n, "seconds": round(gt, 3), "queries_per_s": round(c1.m / gt, 1),
@@ -193,7 +204,8 @@ def main():
             "certificate_pairs": rep["pairs_evaluated"], "violations": bad,
             "unresolved": rep["n_unresolved"], "infeasible": rep["n_infeasible"],
             "kinds": {"hi": rep["n_hi"], "lo": rep["n_lo"], "zero": rep["n_zero"], "rmin": rep["n_rmin"],
-                      "coincident": rep["n_coincident"]}}
+                      "coincident": rep["n_coincident"]},
+            "backward_ms": round(bt * 1e3, 3)}
     if not args.no_greedy and not args.no_batched:
         inst = configs.batch(BATCH_COUNT, grids=BATCH_GRIDS)
         tens = [(torch.tensor(np.c_[x.points, x.values], device=dev), torch.tensor(x.queries, device=dev), x.grid)
@@ -213,6 +225,19 @@ def main():
                           "queries": mq, "batched_s": round(tb, 3), "plain_s": round(tp, 3),
                           "batched_queries_per_s": round(mq / tb, 1), "plain_queries_per_s": round(mq / tp, 1),
                           "speedup": round(tp / tb, 2), "identical_values": same}
+    if not args.no_greedy and not args.no_repair:
+        c3 = configs.csg(grid=REPAIR_GRID, uniform_queries=REPAIR_QUERIES // 2, near_queries=REPAIR_QUERIES // 2)
+        s3 = torch.tensor(np.c_[c3.points, c3.values], device=dev)
+        q3 = torch.tensor(c3.queries, device=dev)
+        r3, rt = wall(lambda: sdfi.repair(s3, q3))
+        rr = r3[-1]
+        progress(f"repair csg{REPAIR_GRID}: {rt:.2f} s, {int(rr['n_removed'])} samples removed")
+        out["repair"] = {"workload": f"CSG pseudo-SDF of 16 primitives, {REPAIR_GRID}^3 samples + {c3.m} scattered "
+                                     "queries (half uniform, half near the zero set)",
+                         "samples": c3.n, "queries": c3.m, "seconds": round(rt, 3),
+                         "points_per_s": round((c3.n + c3.m) / rt, 1), "removed": int(rr["n_removed"]),
+                         "ms": {"witnesses": round(rr["ms_phase"][0], 1), "removal": round(rr["ms_phase"][1], 1),
+                                "rmin": round(rr["ms_phase"][2], 1)}}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
         progress(f"cpu baseline: {out['cpu_baseline']['value']} G pair-evals/s")

@@ -25,6 +25,8 @@ struct Shared {
     double wx[NW][3];
     unsigned long long bound_bits;
     double wlow[NW];
+    int64_t hball[geom::NHOLD];  // balls that held whole search regions (this pass's local numbering)
+    int hnext;
 };
 
 __device__ inline int wid() { return threadIdx.x >> 6; }
@@ -229,14 +231,16 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
         if (tid == 0) {
             S.counter = 0;
             S.bound_bits = __double_as_longlong(bound);
+            S.hnext = 0;
         }
+        if (tid < geom::NHOLD) S.hball[tid] = -1;
         __syncthreads();
         // each wave pulls spheres and keeps its own best
         double wd = INFINITY, wlb = INFINITY, wx[3] = {0.0, 0.0, 0.0};
         int64_t wi = INT64_MAX;
         int wk = 0, wnd = 1;
         double wlow = INFINITY;
-        geom::Holders hold;  // balls that held whole search regions (this pass's local numbering)
+        geom::Holders hold{S.hball, &S.hnext};  // shared by the waves, reset each pass
         const int w = wid();
         // each wave takes PULL candidates at a time: lanes load them and their
         // lower bounds together, then the survivors are searched in list order

@@ -665,13 +665,19 @@ __device__ __noinline__ int lazy_exist_call(const Balls &B, const double *o, dou
     return lazy_exist(B, o, r, hint, kp, kid, cl, ccap, x);
 }
 
-// Recently seen balls that held a whole search region (ball indices, -1 empty).
-constexpr int NHOLD = 4;
+// Recently seen balls that held a whole search region (ball indices, -1
+// empty): a ring of NHOLD entries in LDS shared by the wavefronts of a
+// work-group.  Entries may be replaced while another wave reads them; any
+// ball index read is a valid ball, and the holding test is exact for it.
+constexpr int NHOLD = 32;
 struct Holders {
-    int64_t h[NHOLD] = {-1, -1, -1, -1};
+    int64_t *h;  // NHOLD entries (LDS)
+    int *next;   // ring position (LDS)
     __device__ void push(int64_t f) {
-        for (int j = NHOLD - 1; j > 0; --j) h[j] = h[j - 1];
-        h[0] = f;
+        if ((threadIdx.x & 63) == 0) {
+            const int slot = atomicAdd(next, 1) & (NHOLD - 1);
+            __hip_atomic_store(&h[slot], f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
     }
 };
 
@@ -722,12 +728,17 @@ __device__ inline int lazy_nearest(const Balls &B0, const double *o, double r, c
     // tried on their own first
     int held = 0;
     if (hold && B.use_region) {
-        for (int j = 0; j < NHOLD; ++j) {
-            if (hold->h[j] < 0) continue;
-            Cap ch;
-            const int st = cap_of(B, hold->h[j], o, r, ch);
-            if (st == 2 || (st == 1 && region_held(B, ch))) return 0;
+        // one recent holder per lane
+        int hit = 0;
+        if (lane < NHOLD) {
+            const int64_t f = __hip_atomic_load(&hold->h[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (f >= 0 && f < ball_count(B)) {
+                Cap ch;
+                const int st = cap_of(B, f, o, r, ch);
+                hit = st == 2 || (st == 1 && region_held(B, ch));
+            }
         }
+        if (wor(hit)) return 0;
     }
     int64_t hnew = INT64_MAX;
     wave_cover(B, o, r, v0, -1, &mx, &arg, &whole, &held, hold ? &hnew : nullptr);
