@@ -10,9 +10,13 @@ namespace blk {
 using geom::Balls;
 using geom::Cap;
 
+constexpr int NRAY = 15;  // rays of the minimum valid radius' upper bound
+constexpr int RAYMAX = 16;
+
 template <int NW>
 struct Shared {
     double rd[NW];
+    double rv[NW][RAYMAX];
     int64_t ri[NW];
     int cnt[NW];
     int counter;
@@ -41,6 +45,22 @@ __device__ inline double bmax(double v, Shared<NW> &S) {
     for (int w = 1; w < NW; ++w) r = fmax(r, S.rd[w]);
     __syncthreads();
     return r;
+}
+
+// element-wise block maximum of v[0..K) (K <= RAYMAX)
+template <int NW, int K>
+__device__ inline void bmax_n(double *v, Shared<NW> &S) {
+    for (int k = 0; k < K; ++k) {
+        const double r = geom::wmax(v[k]);
+        if (lane() == 0) S.rv[wid()][k] = r;
+    }
+    __syncthreads();
+    for (int k = 0; k < K; ++k) {
+        double r = S.rv[0][k];
+        for (int w = 1; w < NW; ++w) r = fmax(r, S.rv[w][k]);
+        v[k] = r;
+    }
+    __syncthreads();
 }
 
 template <int NW>
@@ -104,6 +124,83 @@ __device__ inline bool better(double d, int nd, double lb, int64_t i, double d2,
     return i < i2;
 }
 
+// Upper bound of the minimum valid radius from ray exits (see rmin_block);
+// out of line so that its per-ray state does not weigh on the caller's
+// registers.  All threads of the work-group call it.
+template <int NW>
+__device__ __noinline__ double ray_bound(const double *q, int sigma, const double *p4, int64_t N, double tie,
+                                         int64_t deepest, double depth, double known, Shared<NW> &S) {
+    const int tid = threadIdx.x;
+    const int BS = NW * 64;
+    {
+        double dir[NRAY][3];
+        {
+            const double *pd = p4 + 4 * deepest;
+            double u[3] = {q[0] - pd[0], q[1] - pd[1], q[2] - pd[2]};
+            const double un = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            for (int j = 0; j < 3; ++j) dir[0][j] = un > 0.0 ? u[j] / un : (j == 0 ? 1.0 : 0.0);
+            for (int k = 1; k < 7; ++k)
+                for (int j = 0; j < 3; ++j) dir[k][j] = (j == (k - 1) / 2) ? ((k & 1) ? 1.0 : -1.0) : 0.0;
+            const double is3 = 0.57735026918962576451;
+            for (int k = 7; k < NRAY; ++k)
+                for (int j = 0; j < 3; ++j) dir[k][j] = (((k - 7) >> j) & 1) ? -is3 : is3;
+        }
+        double t[NRAY];
+        // the ray away from the deepest centre first; the others only when the
+        // best bound so far (its exit, or `known` from elsewhere) is well beyond
+        // the depth of the deepest ball (a lower bound of the answer), i.e. when
+        // that bound may be loose
+        unsigned live = 1u;
+        bool widened = false;
+        for (int k = 0; k < NRAY; ++k) t[k] = 0.0;
+        double nearest = INFINITY;
+        int wide_steps = 0;
+        for (int it = 0; it < 128; ++it) {
+            if (!live) {
+                if (widened || !(fmin(nearest, known) > 1.25 * depth)) break;
+                widened = true;
+                live = ((1u << NRAY) - 1u) & ~1u;
+            }
+            // an extra ray that has not left the union after a few steps runs
+            // through a long chain of balls: its exit is far and cannot help
+            if (widened && ++wide_steps > 6) break;
+            double step[NRAY];
+            for (int k = 0; k < NRAY; ++k) step[k] = 0.0;
+            for (int64_t c = tid; c < N; c += BS) {
+                const double *p = p4 + 4 * c;
+                if (sign_class(p[3], tie) != sigma) continue;
+                const double R = fabs(p[3]) - tie;
+                if (!(R > 0.0)) continue;
+                for (int k = 0; k < NRAY; ++k) {
+                    if (!((live >> k) & 1u)) continue;
+                    const double w[3] = {q[0] + t[k] * dir[k][0] - p[0], q[1] + t[k] * dir[k][1] - p[1],
+                                         q[2] + t[k] * dir[k][2] - p[2]};
+                    const double cc = w[0] * w[0] + w[1] * w[1] + w[2] * w[2] - R * R;
+                    if (!(cc < 0.0)) continue;
+                    const double bb = dir[k][0] * w[0] + dir[k][1] * w[1] + dir[k][2] * w[2];
+                    step[k] = fmax(step[k], -bb + sqrt(bb * bb - cc));
+                }
+            }
+            bmax_n<NW, NRAY>(step, S);
+            for (int k = 0; k < NRAY; ++k) {
+                if (!((live >> k) & 1u)) continue;
+                if (!(step[k] > 0.0)) {
+                    nearest = fmin(nearest, t[k]);
+                    live &= ~(1u << k);
+                } else {
+                    t[k] += step[k] + 1e-12;  // strictly past the exit of the ball left behind
+                }
+            }
+            for (int k = 0; k < NRAY; ++k)
+                if (((live >> k) & 1u) && !(t[k] < nearest)) live &= ~(1u << k);
+        }
+        // the exit may lie in a tol-thin overlap with an opposite-sign ball,
+        // whose uncovered edge is within sqrt(2 R tol) of it: a margin of 2e-3
+        // keeps the bound above the answer for radii up to 2
+        return nearest < INFINITY ? nearest * (1.0 + 1e-12) + 2e-3 : INFINITY;
+    }
+}
+
 // Minimum valid radius of q for sign sigma against balls rows [0, N) of p4
 // (x, y, z, s) with known uncovered points W (rows may be NaN).  The contour
 // is that of the balls shrunk by the uniqueness tolerance `tie` only, so the
@@ -152,52 +249,23 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
     if (deepest == INT64_MAX) return -2;  // no ball attains the depth (only with NaN data): no answer
     const double wbound = isinf(wbest) ? INFINITY : wbest * (1.0 + 1e-12) + 1e-15;
     double bound = wbound, rbound = INFINITY;
-    // A second upper bound: the exit of the ray from q away from the deepest
-    // centre.  At each point of the ray, jump to the farthest exit among the
-    // balls (shrunk by tie) holding it; the first point no ball holds is off
-    // the union, so the contour is no farther from q than that point.
-    {
-        const double *pd = p4 + 4 * deepest;
-        double dir[3] = {q[0] - pd[0], q[1] - pd[1], q[2] - pd[2]};
-        double dn = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
-        if (!(dn > 0.0)) {
-            dir[0] = 1.0;
-            dir[1] = 0.0;
-            dir[2] = 0.0;
-            dn = 1.0;
-        }
-        for (int j = 0; j < 3; ++j) dir[j] /= dn;
-        double t = 0.0;
-        for (int it = 0; it < 64; ++it) {
-            const double x[3] = {q[0] + t * dir[0], q[1] + t * dir[1], q[2] + t * dir[2]};
-            double step = 0.0;
-            for (int64_t c = tid; c < N; c += BS) {
-                const double *p = p4 + 4 * c;
-                if (sign_class(p[3], tie) != sigma) continue;
-                const double R = fabs(p[3]) - tie;
-                const double w[3] = {x[0] - p[0], x[1] - p[1], x[2] - p[2]};
-                const double cc = w[0] * w[0] + w[1] * w[1] + w[2] * w[2] - R * R;
-                if (!(R > 0.0) || !(cc < 0.0)) continue;
-                const double b = dir[0] * w[0] + dir[1] * w[1] + dir[2] * w[2];
-                step = fmax(step, -b + sqrt(b * b - cc));
-            }
-            step = bmax(step, S);
-            if (!(step > 0.0)) {
-                rbound = t * (1.0 + 1e-12) + 1e-12;
-                bound = fmin(bound, rbound);
-                break;
-            }
-            t += step + 1e-12;  // strictly past the exit of the ball left behind
-        }
-    }
+    // A second upper bound: the nearest exit of NRAY rays from q (away from the
+    // deepest centre, along the axes and the diagonals).  At each point of a
+    // ray, jump to the farthest exit among the balls (shrunk by tie) holding
+    // it; the first point no ball holds is off the union, so the contour is no
+    // farther from q than that point.  The rays advance together, one block
+    // scan per step; a ray stops once it is past the nearest exit found.
+    rbound = ray_bound<NW>(q, sigma, p4, N, tie, deepest, depth, wbound, S);
+    bound = fmin(bound, rbound);
     int64_t *lset = list + (N + 1);
     // Both bounds can fall just short of the answer: a cached witness is only
     // uncovered w.r.t. the tol-shrunk balls, and the ray may leave the sigma
     // union inside a tol-thin overlap with an opposite-sign ball, whose
     // uncovered edge lies within sqrt(2 R tol) of it.  A pass that finds
-    // nothing within its bound moves on to the larger bound plus that margin,
-    // then to no bound at all; what a pass finds within its bound is exact.
-    const double looser = fmax(isinf(wbound) ? 0.0 : wbound, isinf(rbound) ? 0.0 : rbound) + 4e-3;
+    // nothing within its bound moves on to that bound plus a margin of twice
+    // that size, then to no bound at all; what a pass finds within its bound
+    // is exact.
+    const double looser = bound + 4e-3;
     for (int pass = 0; pass < 3; ++pass) {
         // candidate spheres: sigma spheres passing within `bound` of q (deepest first)
         int64_t len = 0, nl = 0;
