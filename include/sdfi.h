@@ -142,7 +142,15 @@ void sdfi_timing_enable(int on);
  * last reset (waits for the recorded events).  Unknown names give 0. */
 sdfi_status sdfi_timing_query(const char *name, double *ms, int64_t *launches);
 
-/* Forget all recorded timings. */
+/* Work counters recorded while timing is enabled, summed since the last
+ * reset (waits for the recorded work).  "sweep_pairs_skipped": query x sample
+ * pairs that the float32 bound sweep of sdfi_bounds ruled out a whole tile at
+ * a time, from the tile's box and value range, without evaluating them (their
+ * values can neither be a bound nor lie within its tie band, so the results
+ * equal those of the full sweep).  Unknown names give 0. */
+sdfi_status sdfi_counter_query(const char *name, int64_t *value);
+
+/* Forget all recorded timings and counters. */
 void sdfi_timing_reset(void);
 
 /* Workspace bytes that entry point `op` needs for n samples and m queries

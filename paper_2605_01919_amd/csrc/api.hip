@@ -27,6 +27,13 @@ std::mutex g_tm;
 bool g_timing = false;
 std::vector<Pending> g_pending;
 std::map<std::string, std::pair<double, int64_t>> g_acc;
+struct PendingCount {
+    std::string name;
+    int64_t *host;  // pinned
+    hipEvent_t done;
+};
+std::vector<PendingCount> g_pcount;
+std::map<std::string, int64_t> g_count;
 
 void drain_locked() {
     for (auto &p : g_pending) {
@@ -40,6 +47,12 @@ void drain_locked() {
         (void)hipEventDestroy(p.b);
     }
     g_pending.clear();
+    for (auto &p : g_pcount) {
+        if (hipEventSynchronize(p.done) == hipSuccess) g_count[p.name] += *p.host;
+        (void)hipEventDestroy(p.done);
+        (void)hipHostFree(p.host);
+    }
+    g_pcount.clear();
 }
 }  // namespace
 
@@ -59,6 +72,24 @@ void KernelTimer::stop() {
     std::lock_guard<std::mutex> lk(g_tm);
     g_pending.push_back({name, a, b});
     a = b = nullptr;
+}
+
+void note_count(const char *n, const int64_t *dev, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_tm);
+    if (!g_timing) return;
+    PendingCount p{n, nullptr, nullptr};
+    if (hipHostMalloc((void **)&p.host, sizeof(int64_t), hipHostMallocDefault) != hipSuccess) return;
+    if (hipEventCreate(&p.done) != hipSuccess) {
+        (void)hipHostFree(p.host);
+        return;
+    }
+    if (hipMemcpyAsync(p.host, dev, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipEventRecord(p.done, st) != hipSuccess) {
+        (void)hipEventDestroy(p.done);
+        (void)hipHostFree(p.host);
+        return;
+    }
+    g_pcount.push_back(p);
 }
 
 sdfi_status read_options(const sdfi_options *opt, sdfi_options *out) {
@@ -131,10 +162,20 @@ sdfi_status sdfi_timing_query(const char *name, double *ms, int64_t *launches) {
     return SDFI_OK;
 }
 
+sdfi_status sdfi_counter_query(const char *name, int64_t *value) {
+    SDFI_CHECK_ARG(name && value, "null argument");
+    std::lock_guard<std::mutex> lk(sdfi::g_tm);
+    sdfi::drain_locked();
+    auto it = sdfi::g_count.find(name);
+    *value = it == sdfi::g_count.end() ? 0 : it->second;
+    return SDFI_OK;
+}
+
 void sdfi_timing_reset(void) {
     std::lock_guard<std::mutex> lk(sdfi::g_tm);
     sdfi::drain_locked();
     sdfi::g_acc.clear();
+    sdfi::g_count.clear();
 }
 
 const char *sdfi_version(void) { return "sdfi 0.1 gfx950"; }

@@ -251,7 +251,9 @@ __device__ inline bool near32(float4 p, const float *qf, int side, float run, fl
 }
 
 // sperm (nullable): tile t holds the samples sperm[t*TILE ...] (sorted order);
-// eps_dev (nullable): the band, computed on the device, replaces eps.
+// eps_dev (nullable): the band, computed on the device, replaces eps;
+// qperm (nullable): wavefront k takes the query qperm[k], whose lists are in
+// slot k (sorted order: neighbouring wavefronts share candidate tiles).
 template <typename T>
 __global__ __launch_bounds__(256) void resolve_kernel(const double *__restrict__ samples, int64_t n,
                                                       const double *__restrict__ queries, int64_t m, T eps,
@@ -259,13 +261,13 @@ __global__ __launch_bounds__(256) void resolve_kernel(const double *__restrict__
                                                       double *hi_out, int32_t *argmax, int32_t *argmin,
                                                       uint32_t *flags, int64_t *overflows,
                                                       const int32_t *__restrict__ sperm, const float *eps_dev,
-                                                      const int32_t *__restrict__ qinv,
+                                                      const int32_t *__restrict__ qperm,
                                                       const float4 *__restrict__ ps32) {
     const int lane = threadIdx.x & 63;
-    const int64_t qi = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-    if (qi >= m) return;
+    const int64_t li = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);  // slot of the lists
+    if (li >= m) return;
     if (eps_dev) eps = (T)*eps_dev;
-    const int64_t li = qinv ? (int64_t)qinv[qi] : qi;  // slot of this query's lists
+    const int64_t qi = qperm ? (int64_t)qperm[li] : li;
     // with the float32 copy (sorted like the tiles), a listed tile's samples go
     // to float64 only when their float32 value is within eps of the float32
     // extreme: every sample within the tie band of the float64 extreme is
@@ -280,7 +282,12 @@ __global__ __launch_bounds__(256) void resolve_kernel(const double *__restrict__
         const T run = o.run[2 * li + side];
         const int64_t lb = (li * 2 + side) * LIST;
         const int nt = full ? (int)((n + TILE - 1) / TILE) : (int)cnt;
-        // exact extreme over the candidate tiles
+        // exact extreme over the candidate tiles; with lists (at most LIST
+        // tiles of TILE = 4 x 64 samples) bit 4 e + r of `pass` marks that
+        // sample lane + 64 r of entry e was evaluated, so that the band count
+        // below revisits only those
+        static_assert(LIST * (TILE / 64) <= 32, "one bit per lane sample of the listed tiles");
+        uint32_t pass = 0;
         double best = side == 0 ? -INFINITY : INFINITY;
         for (int e = 0; e < nt; ++e) {
             int t;
@@ -292,9 +299,10 @@ __global__ __launch_bounds__(256) void resolve_kernel(const double *__restrict__
                 if (!keep) continue;
                 t = o.tiles[lb + e];
             }
-            for (int j = lane; j < TILE; j += 64) {
-                int64_t i = (int64_t)t * TILE + j;
+            for (int r = 0; r < TILE / 64; ++r) {
+                int64_t i = (int64_t)t * TILE + lane + 64 * r;
                 if (i < n && (full || !ps32 || near32(ps32[i], qf, side, (float)run, (float)eps))) {
+                    if (!full && ps32) pass |= 1u << (4 * e + r);
                     const int64_t oi = sperm ? (int64_t)sperm[i] : i;
                     double v = pair_val(samples + 4 * oi, q, side);
                     best = side == 0 ? fmax(best, v) : fmin(best, v);
@@ -305,7 +313,18 @@ __global__ __launch_bounds__(256) void resolve_kernel(const double *__restrict__
         // smallest index within the tie band, and the band's population
         int64_t first = INT64_MAX;
         int inband = 0;
-        for (int e = 0; e < nt; ++e) {
+        for (uint32_t b = pass; b; b &= b - 1) {
+            const int k = __builtin_ctz(b);
+            const int64_t i = (int64_t)o.tiles[lb + k / 4] * TILE + lane + 64 * (k % 4);
+            const int64_t oi = sperm ? (int64_t)sperm[i] : i;
+            double v = pair_val(samples + 4 * oi, q, side);
+            bool in = side == 0 ? (v >= best - tie) : (v <= best + tie);
+            if (in) {
+                inband++;
+                first = oi < first ? oi : first;
+            }
+        }
+        for (int e = 0; e < (full || !ps32 ? nt : 0); ++e) {
             int t;
             if (full) {
                 t = e;
@@ -499,27 +518,29 @@ __global__ void pack_sorted_kernel(const double *__restrict__ samples, const int
     }
 }
 
-// box of each tile of the sorted samples: tbox[2t] = low corner, tbox[2t+1] = high corner
+// box and value range of each tile of the sorted samples: tbox[2t] = (low
+// corner, smallest value), tbox[2t+1] = (high corner, largest value)
 __global__ __launch_bounds__(TILE) void tile_box_kernel(const float4 *__restrict__ ps, int64_t n, float4 *tbox) {
-    __shared__ float wv[TILE / 64][6];
+    __shared__ float wv[TILE / 64][8];
     const int64_t i = (int64_t)blockIdx.x * TILE + threadIdx.x;
-    float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    float v[8] = {INFINITY, INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, -INFINITY};
     if (i < n) {
         const float4 p = ps[i];
-        v[0] = v[3] = p.x;
-        v[1] = v[4] = p.y;
-        v[2] = v[5] = p.z;
+        v[0] = v[4] = p.x;
+        v[1] = v[5] = p.y;
+        v[2] = v[6] = p.z;
+        v[3] = v[7] = p.w;
     }
-    for (int k = 0; k < 6; ++k) v[k] = k < 3 ? wred_min(v[k]) : wred_max(v[k]);
+    for (int k = 0; k < 8; ++k) v[k] = k < 4 ? wred_min(v[k]) : wred_max(v[k]);
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0)
-        for (int k = 0; k < 6; ++k) wv[w][k] = v[k];
+        for (int k = 0; k < 8; ++k) wv[w][k] = v[k];
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int ww = 1; ww < TILE / 64; ++ww)
-            for (int k = 0; k < 6; ++k) wv[0][k] = k < 3 ? fminf(wv[0][k], wv[ww][k]) : fmaxf(wv[0][k], wv[ww][k]);
-        tbox[2 * blockIdx.x] = make_float4(wv[0][0], wv[0][1], wv[0][2], 0.0f);
-        tbox[2 * blockIdx.x + 1] = make_float4(wv[0][3], wv[0][4], wv[0][5], 0.0f);
+            for (int k = 0; k < 8; ++k) wv[0][k] = k < 4 ? fminf(wv[0][k], wv[ww][k]) : fmaxf(wv[0][k], wv[ww][k]);
+        tbox[2 * blockIdx.x] = make_float4(wv[0][0], wv[0][1], wv[0][2], wv[0][3]);
+        tbox[2 * blockIdx.x + 1] = make_float4(wv[0][4], wv[0][5], wv[0][6], wv[0][7]);
     }
 }
 
@@ -531,7 +552,8 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
                                                           const float4 *__restrict__ tbox,
                                                           const double *__restrict__ queries,
                                                           const int32_t *__restrict__ qperm, int64_t m,
-                                                          const Extent *__restrict__ ext, SweepOut<float> o) {
+                                                          const Extent *__restrict__ ext, SweepOut<float> o,
+                                                          unsigned long long *__restrict__ skipped) {
     // a tile is either near (raw samples (x, y, z, s)) or far ((-2 a, |a|^2) with
     // a = p - c, values apart): the two layouts share one LDS array
     __shared__ float4 tilebuf[TILE];
@@ -539,6 +561,7 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
     float4 *const raw = tilebuf;
     float4 *const cen = tilebuf;
     __shared__ float wbox[MQ / 64][6];
+    __shared__ unsigned long long wneed[2][MQ / 64];  // far tiles of a chunk each wavefront needs (two phases)
     __shared__ int32_t ltile[2][LIST][MQ];  // candidate lists of the work-group's queries
     __shared__ float lval[2][LIST][MQ];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -582,105 +605,163 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
     float run_lo = -INFINITY, run_hi = INFINITY;
     uint32_t clo = 0, chi = 0;
     const int ntiles = (n + TILE - 1) / TILE;
+    float wlo_all = -INFINITY, whi_all = INFINITY;  // the wavefront's lowest / highest running extremes
+    unsigned nskip = 0;  // far tiles this wavefront skipped
+    int phase = 0;       // alternates per chunk, so that need masks are not rewritten before all waves read them
+    // One tile: stage it in LDS, reduce it (the matrix path for far tiles, the
+    // direct formula for near ones), note it in the candidate lists.  `act`:
+    // this wavefront needs the tile (a far tile it ruled out is not reduced).
+    // Called with the same (t, far) by all wavefronts of the work-group.
+    auto sweep_tile = [&](int t, bool far, bool act) {
+        const int cnt = min(TILE, n - t * TILE);
+        __syncthreads();
+        if (tid < cnt) {
+            const float4 p = ps[(int64_t)t * TILE + tid];
+            if (far) {
+                const float ax = p.x - cx, ay = p.y - cy, az = p.z - cz;
+                cen[tid] = make_float4(-2.0f * ax, -2.0f * ay, -2.0f * az, ax * ax + ay * ay + az * az);
+                sv[tid] = p.w;
+            } else {
+                raw[tid] = p;
+            }
+        }
+        __syncthreads();
+        float tlo = -INFINITY, thi = INFINITY;
+        if (far && act) {
+            // Running extremes of the four query columns this lane holds, widened
+            // by 2 eps.  A pair with d >= max(s - rl, rh - s) has s - d <= rl and
+            // s + d >= rh: it can neither be near either extreme nor move it, so a
+            // 16 x 16 block where every lane has min d^2 >= T^2 (T built from its
+            // four samples' largest and smallest value) needs no square root.
+            float rl[4], rh[4];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                const int src = 16 * cb + (lane & 15);
+                rl[cb] = __shfl(run_lo, src, 64) - 2.0f * eps;
+                rh[cb] = __shfl(run_hi, src, 64) + 2.0f * eps;
+            }
+            float lo4[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+            float hi4[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+            const float *cenf = reinterpret_cast<const float *>(cen);
+#pragma unroll 2
+            for (int b = 0; b < TILE / 16; ++b) {
+                // A[i][k]: sample 16 b + i, component k (this lane: i = lane & 15, k = lane >> 4)
+                const float a = cenf[4 * (16 * b + (lane & 15)) + (lane >> 4)];
+                // rows of the product held by this lane: samples 16 b + 4 (lane >> 4) + 0..3
+                const float4 s4 = *reinterpret_cast<const float4 *>(&sv[16 * b + 4 * (lane >> 4)]);
+                f32x4 D[4];
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+                    D[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, B[cb], C[cb], 0, 0, 0);
+                const float smax = fmaxf(fmaxf(s4.x, s4.y), fmaxf(s4.z, s4.w));
+                const float smin = fminf(fminf(s4.x, s4.y), fminf(s4.z, s4.w));
+                int need = 0;
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) {
+                    const float dmin2 = fminf(fminf(D[cb][0], D[cb][1]), fminf(D[cb][2], D[cb][3]));
+                    const float T = fmaxf(fmaxf(smax - rl[cb], rh[cb] - smin), 0.0f);
+                    need |= dmin2 < T * T;
+                }
+                if (__any(need)) {
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb) {
+                        const float d0 = __builtin_amdgcn_sqrtf(fabsf(D[cb][0]));
+                        const float d1 = __builtin_amdgcn_sqrtf(fabsf(D[cb][1]));
+                        const float d2 = __builtin_amdgcn_sqrtf(fabsf(D[cb][2]));
+                        const float d3 = __builtin_amdgcn_sqrtf(fabsf(D[cb][3]));
+                        lo4[cb] = fmaxf(fmaxf(lo4[cb], s4.x - d0), s4.y - d1);
+                        lo4[cb] = fmaxf(fmaxf(lo4[cb], s4.z - d2), s4.w - d3);
+                        hi4[cb] = fminf(fminf(hi4[cb], s4.x + d0), s4.y + d1);
+                        hi4[cb] = fminf(fminf(hi4[cb], s4.z + d2), s4.w + d3);
+                    }
+                }
+            }
+            // combine the four row groups holding each query column
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                lo4[cb] = fmaxf(lo4[cb], __shfl_xor(lo4[cb], 16, 64));
+                lo4[cb] = fmaxf(lo4[cb], __shfl_xor(lo4[cb], 32, 64));
+                hi4[cb] = fminf(hi4[cb], __shfl_xor(hi4[cb], 16, 64));
+                hi4[cb] = fminf(hi4[cb], __shfl_xor(hi4[cb], 32, 64));
+            }
+            // this lane's own query is local query `lane`: column block lane >> 4
+            const int mine = lane >> 4;
+            tlo = mine == 0 ? lo4[0] : (mine == 1 ? lo4[1] : (mine == 2 ? lo4[2] : lo4[3]));
+            thi = mine == 0 ? hi4[0] : (mine == 1 ? hi4[1] : (mine == 2 ? hi4[2] : hi4[3]));
+        } else if (!far) {
+            for (int j = 0; j < cnt; ++j) {
+                const float4 p = raw[j];
+                const float dx = qx - p.x, dy = qy - p.y, dz = qz - p.z;
+                const float d = __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz);
+                tlo = fmaxf(tlo, p.w - d);
+                thi = fminf(thi, p.w + d);
+            }
+        }
+        note_tile_lds(0, tid, t, tlo, run_lo, clo, eps, ltile, lval);
+        note_tile_lds(1, tid, t, thi, run_hi, chi, eps, ltile, lval);
+    };
     // Two passes over the tiles: the near ones first (direct formula), so that
     // the running extremes are already close to final when the far tiles are
     // swept on the matrix path and its group test can skip most square roots.
+    // Tiles are classified 64 at a time, one per lane.
+    //
+    // A far tile can be ruled out by a wavefront when every pair with its
+    // queries has s - d < (lowest running lower extreme) - 2 eps and s + d >
+    // (highest running upper extreme) + 2 eps: by the box gap g of the wave's
+    // queries and the tile, when smax - g and smin + g clear those.  Such pairs
+    // can neither move an extreme nor enter its band (the same margin as the
+    // group test), so the results are those of the full sweep.  The work-group
+    // stages only the tiles that one of its wavefronts needs.
     for (int pass = 0; pass < 2; ++pass) {
-        for (int t = 0; t < ntiles; ++t) {
-            const int cnt = min(TILE, n - t * TILE);
-            const float4 tl = tbox[2 * t], th = tbox[2 * t + 1];
-            const float gx = fmaxf(0.0f, fmaxf(tl.x - qhi[0], qlo[0] - th.x));
-            const float gy = fmaxf(0.0f, fmaxf(tl.y - qhi[1], qlo[1] - th.y));
-            const float gz = fmaxf(0.0f, fmaxf(tl.z - qhi[2], qlo[2] - th.z));
-            const float gap = sqrtf(gx * gx + gy * gy + gz * gz);
-            const bool far = far_ok && cnt == TILE && gap > 0.0f && gap >= delta;
-            if (far != (pass == 1)) continue;  // uniform over the work-group
-            __syncthreads();
-            if (tid < cnt) {
-                const float4 p = ps[(int64_t)t * TILE + tid];
-                if (far) {
-                    const float ax = p.x - cx, ay = p.y - cy, az = p.z - cz;
-                    cen[tid] = make_float4(-2.0f * ax, -2.0f * ay, -2.0f * az, ax * ax + ay * ay + az * az);
-                    sv[tid] = p.w;
-                } else {
-                    raw[tid] = p;
+        for (int c0 = 0; c0 < ntiles; c0 += 64) {
+            const int t = c0 + lane;
+            bool in_pass = false, need = false;
+            if (t < ntiles) {
+                const int cnt = min(TILE, n - t * TILE);
+                const float4 tl = tbox[2 * t], th = tbox[2 * t + 1];
+                const float gx = fmaxf(0.0f, fmaxf(tl.x - qhi[0], qlo[0] - th.x));
+                const float gy = fmaxf(0.0f, fmaxf(tl.y - qhi[1], qlo[1] - th.y));
+                const float gz = fmaxf(0.0f, fmaxf(tl.z - qhi[2], qlo[2] - th.z));
+                const float gap = sqrtf(gx * gx + gy * gy + gz * gz);
+                const bool far = far_ok && cnt == TILE && gap > 0.0f && gap >= delta;
+                in_pass = far == (pass == 1);
+                need = in_pass;
+                if (in_pass && far) {
+                    const float wx = fmaxf(0.0f, fmaxf(tl.x - wbox[w][3], wbox[w][0] - th.x));
+                    const float wy = fmaxf(0.0f, fmaxf(tl.y - wbox[w][4], wbox[w][1] - th.y));
+                    const float wz = fmaxf(0.0f, fmaxf(tl.z - wbox[w][5], wbox[w][2] - th.z));
+                    const float wgap = sqrtf(wx * wx + wy * wy + wz * wz) * (1.0f - 8.0f * U32);
+                    need = !((th.w - wgap < wlo_all - 2.0f * eps) && (tl.w + wgap > whi_all + 2.0f * eps));
                 }
             }
-            __syncthreads();
-            float tlo = -INFINITY, thi = INFINITY;
-            if (far) {
-                // Running extremes of the four query columns this lane holds, widened
-                // by 2 eps.  A pair with d >= max(s - rl, rh - s) has s - d <= rl and
-                // s + d >= rh: it can neither be near either extreme nor move it, so a
-                // 16 x 16 block where every lane has min d^2 >= T^2 (T built from its
-                // four samples' largest and smallest value) needs no square root.
-                float rl[4], rh[4];
-#pragma unroll
-                for (int cb = 0; cb < 4; ++cb) {
-                    const int src = 16 * cb + (lane & 15);
-                    rl[cb] = __shfl(run_lo, src, 64) - 2.0f * eps;
-                    rh[cb] = __shfl(run_hi, src, 64) + 2.0f * eps;
-                }
-                float lo4[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
-                float hi4[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
-                const float *cenf = reinterpret_cast<const float *>(cen);
-#pragma unroll 2
-                for (int b = 0; b < TILE / 16; ++b) {
-                    // A[i][k]: sample 16 b + i, component k (this lane: i = lane & 15, k = lane >> 4)
-                    const float a = cenf[4 * (16 * b + (lane & 15)) + (lane >> 4)];
-                    // rows of the product held by this lane: samples 16 b + 4 (lane >> 4) + 0..3
-                    const float4 s4 = *reinterpret_cast<const float4 *>(&sv[16 * b + 4 * (lane >> 4)]);
-                    f32x4 D[4];
-#pragma unroll
-                    for (int cb = 0; cb < 4; ++cb)
-                        D[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, B[cb], C[cb], 0, 0, 0);
-                    const float smax = fmaxf(fmaxf(s4.x, s4.y), fmaxf(s4.z, s4.w));
-                    const float smin = fminf(fminf(s4.x, s4.y), fminf(s4.z, s4.w));
-                    int need = 0;
-#pragma unroll
-                    for (int cb = 0; cb < 4; ++cb) {
-                        const float dmin2 = fminf(fminf(D[cb][0], D[cb][1]), fminf(D[cb][2], D[cb][3]));
-                        const float T = fmaxf(fmaxf(smax - rl[cb], rh[cb] - smin), 0.0f);
-                        need |= dmin2 < T * T;
-                    }
-                    if (__any(need)) {
-#pragma unroll
-                        for (int cb = 0; cb < 4; ++cb) {
-                            const float d0 = __builtin_amdgcn_sqrtf(fabsf(D[cb][0]));
-                            const float d1 = __builtin_amdgcn_sqrtf(fabsf(D[cb][1]));
-                            const float d2 = __builtin_amdgcn_sqrtf(fabsf(D[cb][2]));
-                            const float d3 = __builtin_amdgcn_sqrtf(fabsf(D[cb][3]));
-                            lo4[cb] = fmaxf(fmaxf(lo4[cb], s4.x - d0), s4.y - d1);
-                            lo4[cb] = fmaxf(fmaxf(lo4[cb], s4.z - d2), s4.w - d3);
-                            hi4[cb] = fminf(fminf(hi4[cb], s4.x + d0), s4.y + d1);
-                            hi4[cb] = fminf(fminf(hi4[cb], s4.z + d2), s4.w + d3);
-                        }
-                    }
-                }
-                // combine the four row groups holding each query column
-#pragma unroll
-                for (int cb = 0; cb < 4; ++cb) {
-                    lo4[cb] = fmaxf(lo4[cb], __shfl_xor(lo4[cb], 16, 64));
-                    lo4[cb] = fmaxf(lo4[cb], __shfl_xor(lo4[cb], 32, 64));
-                    hi4[cb] = fminf(hi4[cb], __shfl_xor(hi4[cb], 16, 64));
-                    hi4[cb] = fminf(hi4[cb], __shfl_xor(hi4[cb], 32, 64));
-                }
-                // this lane's own query is local query `lane`: column block lane >> 4
-                const int mine = lane >> 4;
-                tlo = mine == 0 ? lo4[0] : (mine == 1 ? lo4[1] : (mine == 2 ? lo4[2] : lo4[3]));
-                thi = mine == 0 ? hi4[0] : (mine == 1 ? hi4[1] : (mine == 2 ? hi4[2] : hi4[3]));
-            } else {
-                for (int j = 0; j < cnt; ++j) {
-                    const float4 p = raw[j];
-                    const float dx = qx - p.x, dy = qy - p.y, dz = qz - p.z;
-                    const float d = __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz);
-                    tlo = fmaxf(tlo, p.w - d);
-                    thi = fminf(thi, p.w + d);
-                }
+            const unsigned long long inpass = __ballot(in_pass);  // the same in every wavefront
+            const unsigned long long mine = __ballot(need);
+            unsigned long long todo = inpass;
+            if (pass == 1) {
+                nskip += (unsigned)__popcll(inpass & ~mine);
+                if (lane == 0) wneed[phase][w] = mine;
+                __syncthreads();
+                todo = wneed[phase][0] | wneed[phase][1] | wneed[phase][2] | wneed[phase][3];
+                phase ^= 1;
             }
-            note_tile_lds(0, tid, t, tlo, run_lo, clo, eps, ltile, lval);
-            note_tile_lds(1, tid, t, thi, run_hi, chi, eps, ltile, lval);
+            for (; todo; todo &= todo - 1) {
+                const int k = __builtin_ctzll(todo);
+                sweep_tile(c0 + k, pass == 1, ((mine >> k) & 1ull) != 0);
+            }
+            if (pass == 1) {
+                wlo_all = wred_min(run_lo);
+                whi_all = wred_max(run_hi);
+            }
         }
+        if (pass == 0) {
+            wlo_all = wred_min(run_lo);
+            whi_all = wred_max(run_hi);
+        }
+    }
+    // pairs ruled out without evaluation (stand-in lanes past m not counted)
+    {
+        const int vl = (int)min((int64_t)64, max((int64_t)0, m - ((int64_t)blockIdx.x * MQ + 64 * w)));
+        if (lane == 0 && nskip) atomicAdd(skipped, (unsigned long long)nskip * (unsigned long long)(vl * TILE));
     }
     // lists and extremes leave in sorted order (slot sq), contiguous per work-group
     if (valid) {
@@ -706,18 +787,12 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
     }
 }
 
-// qinv[qperm[k]] = k
-__global__ void invert_kernel(const int32_t *__restrict__ perm, int64_t k, int32_t *__restrict__ inv) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < k) inv[perm[i]] = (int32_t)i;
-}
-
 // workspace of the sorted float32 path
 struct SortedBufs {
     ExtPart *parts;
     Extent *ext;
     uint32_t *keys_in, *keys_out;
-    int32_t *idx_in, *sperm, *qperm, *qinv;
+    int32_t *idx_in, *sperm, *qperm;
     float4 *ps, *tbox;
     void *cub;
     size_t cub_bytes;
@@ -740,7 +815,6 @@ SortedBufs carve_sorted(Carver &c, int64_t n, int64_t m) {
     b.idx_in = c.take<int32_t>(k);
     b.sperm = c.take<int32_t>(n);
     b.qperm = c.take<int32_t>(m);
-    b.qinv = c.take<int32_t>(m);
     b.ps = c.take<float4>(n);
     b.tbox = c.take<float4>(2 * ((n + TILE - 1) / TILE));
     b.cub_bytes = std::max(cub_sort_bytes(n), cub_sort_bytes(m));
@@ -752,7 +826,7 @@ template <typename T>
 struct SweepBufs {
     SweepOut<T> o;
     Pt4<T> *pts;
-    int64_t *overflows;
+    int64_t *overflows;  // [0] list overflows, [1] pairs the sorted sweep skipped
 };
 
 template <typename T>
@@ -763,7 +837,7 @@ SweepBufs<T> carve_sweep(Carver &c, int64_t n, int64_t m) {
     b.o.count = c.take<uint32_t>(2 * m);
     b.o.tiles = c.take<int32_t>(2 * m * LIST);
     b.o.vals = c.take<T>(2 * m * LIST);
-    b.overflows = c.take<int64_t>(1);
+    b.overflows = c.take<int64_t>(2);
     return b;
 }
 
@@ -783,7 +857,7 @@ sdfi_status launch(const double *samples, int64_t n, const double *queries, int6
     } else {
         pts = reinterpret_cast<const Pt4<T> *>(samples);
     }
-    SDFI_HIP(hipMemsetAsync(b.overflows, 0, sizeof(int64_t), st));
+    SDFI_HIP(hipMemsetAsync(b.overflows, 0, 2 * sizeof(int64_t), st));
     const int64_t per = (int64_t)BT * QPT;
     KernelTimer t1("sweep", st);
     sweep_kernel<T, QPT><<<(unsigned)((m + per - 1) / per), BT, 0, st>>>(pts, (int)n, queries, m, eps, b.o);
@@ -821,18 +895,19 @@ sdfi_status launch_sorted(const double *samples, int64_t n, const double *querie
     morton_kernel<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(queries, 3, m, sb.ext, sb.keys_in, sb.idx_in);
     SDFI_HIP(hipcub::DeviceRadixSort::SortPairs(sb.cub, sb.cub_bytes, sb.keys_in, sb.keys_out, sb.idx_in, sb.qperm,
                                                 (int)m, 0, 30, st));
-    invert_kernel<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(sb.qperm, m, sb.qinv);
     SDFI_HIP(hipGetLastError());
-    SDFI_HIP(hipMemsetAsync(b.overflows, 0, sizeof(int64_t), st));
+    SDFI_HIP(hipMemsetAsync(b.overflows, 0, 2 * sizeof(int64_t), st));
     KernelTimer t1("sweep", st);
     sweep_sorted_kernel<<<(unsigned)((m + MQ - 1) / MQ), MQ, 0, st>>>(sb.ps, (int)n, sb.tbox, queries, sb.qperm, m,
-                                                                       sb.ext, b.o);
+                                                                       sb.ext, b.o,
+                                                                       reinterpret_cast<unsigned long long *>(b.overflows + 1));
     t1.stop();
+    note_count("sweep_pairs_skipped", b.overflows + 1, st);
     SDFI_HIP(hipGetLastError());
     KernelTimer t2("resolve", st);
     resolve_kernel<float><<<(unsigned)((m + 3) / 4), 256, 0, st>>>(samples, n, queries, m, 0.0f, b.o, opt.tol,
                                                                     opt.tie_tol, lo, hi, argmax, argmin, flags,
-                                                                    b.overflows, sb.sperm, &sb.ext->eps, sb.qinv, sb.ps);
+                                                                    b.overflows, sb.sperm, &sb.ext->eps, sb.qperm, sb.ps);
     t2.stop();
     SDFI_HIP(hipGetLastError());
     if (overflow_count) {

@@ -41,6 +41,10 @@ struct KernelTimer {
     void stop();
 };
 
+// While timing is enabled: add the device int64 at `dev` (read once the work
+// queued on `st` so far has finished) to the counter `name`.
+void note_count(const char *name, const int64_t *dev, hipStream_t st);
+
 // Validated copy of the caller's options (defaults when opt == NULL).
 sdfi_status read_options(const sdfi_options *opt, sdfi_options *out);
 

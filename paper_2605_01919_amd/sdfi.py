@@ -73,7 +73,7 @@ def lib():
 
 
 EXPORTS = ["sdfi_default_options", "sdfi_last_error", "sdfi_version", "sdfi_timing_enable", "sdfi_timing_query",
-           "sdfi_timing_reset", "sdfi_workspace_size", "sdfi_bounds",
+           "sdfi_counter_query", "sdfi_timing_reset", "sdfi_workspace_size", "sdfi_bounds",
            "sdfi_certify", "sdfi_refinement_order", "sdfi_sample_witnesses", "sdfi_greedy_interpolate",
            "sdfi_greedy_interpolate_batched", "sdfi_min_valid_radius", "sdfi_repair", "sdfi_greedy_backward"]
 
@@ -133,6 +133,13 @@ def timing_read(names=("sweep", "resolve", "certify", "greedy", "witness", "rmin
         _check(lib().sdfi_timing_query(nm.encode(), ctypes.byref(ms), ctypes.byref(cnt)), "sdfi_timing_query")
         out[nm] = (ms.value, cnt.value)
     return out
+
+
+def counter_read(name):
+    """Work counter `name` recorded since timing() was enabled (see sdfi_counter_query)."""
+    v = ctypes.c_int64()
+    _check(lib().sdfi_counter_query(name.encode(), ctypes.byref(v)), "sdfi_counter_query")
+    return v.value
 
 
 def workspace(op, n, m, opt):
