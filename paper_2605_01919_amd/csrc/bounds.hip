@@ -13,9 +13,12 @@
 // exact.  A list that would hold more than LIST near-extreme tiles marks the
 // query for a full float64 rescan.
 //
-// Pass 2 (resolve): one wavefront per query recomputes its listed tiles in
-// float64 (or all samples after an overflow), takes the exact extreme and
-// the smallest index within tie_tol of it, and writes the flags.
+// Pass 2 (resolve): the listed tiles are recomputed in float64 (after an
+// overflow every tile that can reach the band), giving the exact extreme and
+// the smallest index within tie_tol of it, and the flags.  The float64 mode
+// does this with one wavefront per query; the sorted float32 sweep resolves
+// its own queries at its end, one lane per query, and leaves only the
+// queries whose lists overflowed to a wavefront each.
 //
 // float32 mode runs pass 1 on spatially sorted data (Morton order of samples
 // and of queries, so a tile and a work-group's 256 queries are compact
@@ -242,6 +245,34 @@ __device__ inline int wave_sum(int v) {
 
 __device__ inline int sign_class(double s, double tie) { return s > tie ? 1 : (s < -tie ? -1 : 0); }
 
+struct BoundsOut {
+    double *lo, *hi;
+    int32_t *argmax, *argmin;
+    uint32_t *flags;
+};
+
+// Outputs of query qi from its exact extremes, the smallest indices within
+// their tie bands (INT64_MAX: none), the bands' populations and the values of
+// the two indexed samples.
+__device__ inline void write_query(int64_t qi, double lo, double hi, int64_t a, int64_t b, int tied_lo, int tied_hi,
+                                   double s_a, double s_b, int64_t n, double tol, double tie, const BoundsOut &out) {
+    // no candidate at all only happens with NaN inputs: report index -1
+    const bool have_a = a >= 0 && a < n, have_b = b >= 0 && b < n;
+    out.lo[qi] = lo;
+    out.hi[qi] = hi;
+    out.argmax[qi] = have_a ? (int32_t)a : -1;
+    out.argmin[qi] = have_b ? (int32_t)b : -1;
+    uint32_t f = 0;
+    if (lo > hi + tol) f |= SDFI_FLAG_INFEASIBLE;
+    if (lo > tol) f |= SDFI_FLAG_INSIDE_POS;
+    if (hi < -tol) f |= SDFI_FLAG_INSIDE_NEG;
+    if (tied_lo > 1) f |= SDFI_FLAG_TIE_LO;
+    if (tied_hi > 1) f |= SDFI_FLAG_TIE_HI;
+    if (have_b && sign_class(hi, tie) * sign_class(s_b, tie) < 0) f |= SDFI_FLAG_HI_OPPOSITE;
+    if (have_a && sign_class(lo, tie) * sign_class(s_a, tie) < 0) f |= SDFI_FLAG_LO_OPPOSITE;
+    out.flags[qi] = f;
+}
+
 // float32 value of one pair (the sweep's direct formula) within eps of the
 // float32 extreme `run` of its side
 __device__ inline bool near32(float4 p, const float *qf, int side, float run, float eps) {
@@ -250,23 +281,18 @@ __device__ inline bool near32(float4 p, const float *qf, int side, float run, fl
     return side == 0 ? (p.w - d >= run - eps) : (p.w + d <= run + eps);
 }
 
+// One query, one wavefront: the lists in slot li.
 // sperm (nullable): tile t holds the samples sperm[t*TILE ...] (sorted order);
-// eps_dev (nullable): the band, computed on the device, replaces eps;
-// qperm (nullable): wavefront k takes the query qperm[k], whose lists are in
-// slot k (sorted order: neighbouring wavefronts share candidate tiles).
+// qperm (nullable): the lists of slot li belong to query qperm[li];
+// ps32 (nullable): float32 copy of the samples in tile order, for the screen;
+// tbox (nullable, with ps32): box and value range of each tile.
 template <typename T>
-__global__ __launch_bounds__(256) void resolve_kernel(const double *__restrict__ samples, int64_t n,
-                                                      const double *__restrict__ queries, int64_t m, T eps,
-                                                      SweepOut<T> o, double tol, double tie, double *lo_out,
-                                                      double *hi_out, int32_t *argmax, int32_t *argmin,
-                                                      uint32_t *flags, int64_t *overflows,
-                                                      const int32_t *__restrict__ sperm, const float *eps_dev,
-                                                      const int32_t *__restrict__ qperm,
-                                                      const float4 *__restrict__ ps32) {
+__device__ inline void resolve_slot(int64_t li, const double *__restrict__ samples, int64_t n,
+                                    const double *__restrict__ queries, T eps, const SweepOut<T> &o, double tol,
+                                    double tie, const BoundsOut &out, int64_t *overflows,
+                                    const int32_t *__restrict__ sperm, const int32_t *__restrict__ qperm,
+                                    const float4 *__restrict__ ps32, const float4 *__restrict__ tbox) {
     const int lane = threadIdx.x & 63;
-    const int64_t li = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);  // slot of the lists
-    if (li >= m) return;
-    if (eps_dev) eps = (T)*eps_dev;
     const int64_t qi = qperm ? (int64_t)qperm[li] : li;
     // with the float32 copy (sorted like the tiles), a listed tile's samples go
     // to float64 only when their float32 value is within eps of the float32
@@ -281,71 +307,81 @@ __global__ __launch_bounds__(256) void resolve_kernel(const double *__restrict__
         const bool full = (cnt & OVERFLOW_BIT) != 0;
         const T run = o.run[2 * li + side];
         const int64_t lb = (li * 2 + side) * LIST;
-        const int nt = full ? (int)((n + TILE - 1) / TILE) : (int)cnt;
-        // exact extreme over the candidate tiles; with lists (at most LIST
+        const int ntiles = (int)((n + TILE - 1) / TILE);
+        // Calls fn(t, e) for every tile t to look at: the kept entries e of the
+        // list, or after an overflow every tile (e = -1) that can hold a sample
+        // passing the float32 screen, by the tile's box and value range (the
+        // margin of the sweep's own tile test: a tile ruled out holds only
+        // samples the screen would drop, so the results do not change).
+        auto for_tiles = [&](auto &&fn) {
+            if (!full) {
+                for (int e = 0; e < (int)cnt; ++e) {
+                    T v = o.vals[lb + e];
+                    if (side == 0 ? (v >= run - eps) : (v <= run + eps)) fn(o.tiles[lb + e], e);
+                }
+            } else if (ps32 && tbox) {
+                for (int c0 = 0; c0 < ntiles; c0 += 64) {
+                    const int t = c0 + lane;
+                    bool reach = false;
+                    if (t < ntiles) {
+                        const float4 tl = tbox[2 * t], th = tbox[2 * t + 1];
+                        const float gx = fmaxf(0.0f, fmaxf(tl.x - qf[0], qf[0] - th.x));
+                        const float gy = fmaxf(0.0f, fmaxf(tl.y - qf[1], qf[1] - th.y));
+                        const float gz = fmaxf(0.0f, fmaxf(tl.z - qf[2], qf[2] - th.z));
+                        const float gap = sqrtf(gx * gx + gy * gy + gz * gz) * (1.0f - 8.0f * 5.9604645e-8f);
+                        reach = side == 0 ? !(th.w - gap < (float)run - 2.0f * (float)eps)
+                                          : !(tl.w + gap > (float)run + 2.0f * (float)eps);
+                    }
+                    for (unsigned long long mk = __ballot(reach); mk; mk &= mk - 1) fn(c0 + __builtin_ctzll(mk), -1);
+                }
+            } else {
+                for (int t = 0; t < ntiles; ++t) fn(t, -1);
+            }
+        };
+        // exact extreme over the candidate tiles (after an overflow the float32
+        // screen still holds, `run` being the extreme of every evaluated pair
+        // and the pairs ruled out lying below it); with a list (at most LIST
         // tiles of TILE = 4 x 64 samples) bit 4 e + r of `pass` marks that
         // sample lane + 64 r of entry e was evaluated, so that the band count
         // below revisits only those
         static_assert(LIST * (TILE / 64) <= 32, "one bit per lane sample of the listed tiles");
         uint32_t pass = 0;
         double best = side == 0 ? -INFINITY : INFINITY;
-        for (int e = 0; e < nt; ++e) {
-            int t;
-            if (full) {
-                t = e;
-            } else {
-                T v = o.vals[lb + e];
-                bool keep = side == 0 ? (v >= run - eps) : (v <= run + eps);
-                if (!keep) continue;
-                t = o.tiles[lb + e];
-            }
+        for_tiles([&](int t, int e) {
             for (int r = 0; r < TILE / 64; ++r) {
                 int64_t i = (int64_t)t * TILE + lane + 64 * r;
-                if (i < n && (full || !ps32 || near32(ps32[i], qf, side, (float)run, (float)eps))) {
-                    if (!full && ps32) pass |= 1u << (4 * e + r);
+                if (i < n && (!ps32 || near32(ps32[i], qf, side, (float)run, (float)eps))) {
+                    if (e >= 0 && ps32) pass |= 1u << (4 * e + r);
                     const int64_t oi = sperm ? (int64_t)sperm[i] : i;
                     double v = pair_val(samples + 4 * oi, q, side);
                     best = side == 0 ? fmax(best, v) : fmin(best, v);
                 }
             }
-        }
+        });
         best = side == 0 ? wave_max(best) : wave_min(best);
         // smallest index within the tie band, and the band's population
         int64_t first = INT64_MAX;
         int inband = 0;
-        for (uint32_t b = pass; b; b &= b - 1) {
-            const int k = __builtin_ctz(b);
-            const int64_t i = (int64_t)o.tiles[lb + k / 4] * TILE + lane + 64 * (k % 4);
+        auto band = [&](int64_t i) {
             const int64_t oi = sperm ? (int64_t)sperm[i] : i;
             double v = pair_val(samples + 4 * oi, q, side);
-            bool in = side == 0 ? (v >= best - tie) : (v <= best + tie);
-            if (in) {
+            if (side == 0 ? (v >= best - tie) : (v <= best + tie)) {
                 inband++;
                 first = oi < first ? oi : first;
             }
-        }
-        for (int e = 0; e < (full || !ps32 ? nt : 0); ++e) {
-            int t;
-            if (full) {
-                t = e;
-            } else {
-                T v = o.vals[lb + e];
-                bool keep = side == 0 ? (v >= run - eps) : (v <= run + eps);
-                if (!keep) continue;
-                t = o.tiles[lb + e];
+        };
+        if (!full && ps32) {
+            for (uint32_t b = pass; b; b &= b - 1) {
+                const int k = __builtin_ctz(b);
+                band((int64_t)o.tiles[lb + k / 4] * TILE + lane + 64 * (k % 4));
             }
-            for (int j = lane; j < TILE; j += 64) {
-                int64_t i = (int64_t)t * TILE + j;
-                if (i < n && (full || !ps32 || near32(ps32[i], qf, side, (float)run, (float)eps))) {
-                    const int64_t oi = sperm ? (int64_t)sperm[i] : i;
-                    double v = pair_val(samples + 4 * oi, q, side);
-                    bool in = side == 0 ? (v >= best - tie) : (v <= best + tie);
-                    if (in) {
-                        inband++;
-                        first = oi < first ? oi : first;
-                    }
+        } else {
+            for_tiles([&](int t, int) {
+                for (int r = 0; r < TILE / 64; ++r) {
+                    int64_t i = (int64_t)t * TILE + lane + 64 * r;
+                    if (i < n && (!ps32 || near32(ps32[i], qf, side, (float)run, (float)eps))) band(i);
                 }
-            }
+            });
         }
         ext[side] = best;
         arg[side] = wave_min_i64(first);
@@ -353,23 +389,41 @@ __global__ __launch_bounds__(256) void resolve_kernel(const double *__restrict__
         if (full && lane == 0) atomicAdd((unsigned long long *)overflows, 1ull);
     }
     if (lane == 0) {
-        double lo = ext[0], hi = ext[1];
-        // no candidate at all only happens with NaN inputs: report index -1
-        const bool have_a = arg[0] >= 0 && arg[0] < n, have_b = arg[1] >= 0 && arg[1] < n;
-        lo_out[qi] = lo;
-        hi_out[qi] = hi;
-        argmax[qi] = have_a ? (int32_t)arg[0] : -1;
-        argmin[qi] = have_b ? (int32_t)arg[1] : -1;
-        uint32_t f = 0;
-        if (lo > hi + tol) f |= SDFI_FLAG_INFEASIBLE;
-        if (lo > tol) f |= SDFI_FLAG_INSIDE_POS;
-        if (hi < -tol) f |= SDFI_FLAG_INSIDE_NEG;
-        if (tied[0] > 1) f |= SDFI_FLAG_TIE_LO;
-        if (tied[1] > 1) f |= SDFI_FLAG_TIE_HI;
-        if (have_b && sign_class(hi, tie) * sign_class(samples[4 * arg[1] + 3], tie) < 0) f |= SDFI_FLAG_HI_OPPOSITE;
-        if (have_a && sign_class(lo, tie) * sign_class(samples[4 * arg[0] + 3], tie) < 0) f |= SDFI_FLAG_LO_OPPOSITE;
-        flags[qi] = f;
+        const double s_a = arg[0] >= 0 && arg[0] < n ? samples[4 * arg[0] + 3] : 0.0;
+        const double s_b = arg[1] >= 0 && arg[1] < n ? samples[4 * arg[1] + 3] : 0.0;
+        write_query(qi, ext[0], ext[1], arg[0], arg[1], tied[0], tied[1], s_a, s_b, n, tol, tie, out);
     }
+}
+
+// one wavefront per query slot
+template <typename T>
+__global__ __launch_bounds__(256) void resolve_kernel(const double *__restrict__ samples, int64_t n,
+                                                      const double *__restrict__ queries, int64_t m, T eps,
+                                                      SweepOut<T> o, double tol, double tie, BoundsOut out,
+                                                      int64_t *overflows) {
+    const int64_t li = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    if (li >= m) return;
+    resolve_slot<T>(li, samples, n, queries, eps, o, tol, tie, out, overflows, nullptr, nullptr, nullptr, nullptr);
+}
+
+// the slots listed by the sorted sweep (queries whose candidate lists
+// overflowed): a fixed grid of wavefronts strides over the list, whose length
+// is read on the device (zero: every wavefront exits at once)
+__global__ __launch_bounds__(256) void resolve_list_kernel(const double *__restrict__ samples, int64_t n,
+                                                           const double *__restrict__ queries,
+                                                           const float *__restrict__ eps_dev, SweepOut<float> o,
+                                                           double tol, double tie, BoundsOut out,
+                                                           int64_t *overflows, const int32_t *__restrict__ list,
+                                                           const unsigned long long *__restrict__ list_len,
+                                                           const int32_t *__restrict__ sperm,
+                                                           const int32_t *__restrict__ qperm,
+                                                           const float4 *__restrict__ ps32,
+                                                           const float4 *__restrict__ tbox) {
+    const int64_t len = (int64_t)*list_len;
+    const float eps = *eps_dev;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
+    for (int64_t k = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); k < len; k += waves)
+        resolve_slot<float>(list[k], samples, n, queries, eps, o, tol, tie, out, overflows, sperm, qperm, ps32, tbox);
 }
 
 // ---- float32 sweep over spatially sorted data ----
@@ -377,6 +431,7 @@ __global__ __launch_bounds__(256) void resolve_kernel(const double *__restrict__
 constexpr int MQ = 256;             // queries per work-group of the sorted sweep (4 wavefronts x 64)
 static_assert(MQ == 256, "the LDS candidate lists are laid out for 256 queries");
 constexpr int EXT_BLOCKS = 256;     // partial reductions of the extent
+constexpr int RESOLVE_LIST_BLOCKS = 256;  // work-groups of the overflow resolve
 constexpr float U32 = 5.9604645e-8f;  // unit roundoff of float32
 
 // Extent of samples and queries and the constants derived from it.
@@ -510,11 +565,90 @@ __global__ void morton_kernel(const double *__restrict__ pts, int stride, int64_
 
 // float32 copy of the samples in sorted order
 __global__ void pack_sorted_kernel(const double *__restrict__ samples, const int32_t *__restrict__ perm, int64_t n,
-                                   float4 *__restrict__ out) {
+                                   float4 *__restrict__ out, double *__restrict__ out64) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < n) {
         const double *p = samples + 4 * (int64_t)perm[i];
-        out[i] = make_float4((float)p[0], (float)p[1], (float)p[2], (float)p[3]);
+        const double x = p[0], y = p[1], z = p[2], v = p[3];
+        out[i] = make_float4((float)x, (float)y, (float)z, (float)v);
+        out64[4 * i] = x;
+        out64[4 * i + 1] = y;
+        out64[4 * i + 2] = z;
+        out64[4 * i + 3] = v;
+    }
+}
+
+// What the sorted sweep needs to resolve its queries itself.
+struct Fused {
+    const double *ps64;    // float64 samples in tile order (x, y, z, s)
+    const int32_t *sperm;  // tile order -> input index
+    double tol, tie;
+    BoundsOut out;
+    int32_t *ovf_list;               // slots whose lists overflowed, for resolve_list_kernel
+    unsigned long long *ovf_len;
+};
+
+// Exact extreme of one side of one query by one lane, over the tiles its list
+// keeps (entries within eps of the float32 extreme `run`): samples whose
+// float32 value (the direct formula) is within eps of `run` get their
+// float64 value; the smallest input index within `tie` of the float64
+// extreme, the band's population and that sample's value follow.  The first
+// two survivors are kept in registers for the band count; with more, the
+// kept tiles are screened again.
+__device__ inline void resolve_lane(int side, const float *qf, const double *q, float run, float eps, uint32_t cnt,
+                                    int lq, const int32_t (*lt)[LIST][256], const float (*lv)[LIST][256],
+                                    const float4 *__restrict__ ps, int64_t n, const Fused &F, double &best,
+                                    int64_t &first, int &inband, double &s_first) {
+    best = side == 0 ? -INFINITY : INFINITY;
+    int nc = 0;
+    int64_t c0 = 0, c1 = 0;
+    for (uint32_t e = 0; e < cnt; ++e) {
+        const float v = lv[side][e][lq];
+        if (!(side == 0 ? (v >= run - eps) : (v <= run + eps))) continue;
+        const int64_t base = (int64_t)lt[side][e][lq] * TILE;
+        const int len = (int)min((int64_t)TILE, n - base);
+        for (int j0 = 0; j0 < len; j0 += 4) {
+            float4 p4[4];  // four loads in flight
+#pragma unroll
+            for (int r = 0; r < 4; ++r) p4[r] = ps[base + min(j0 + r, len - 1)];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (j0 + r >= len || !near32(p4[r], qf, side, run, eps)) continue;
+                const int64_t i = base + j0 + r;
+                const double v64 = pair_val(F.ps64 + 4 * i, q, side);
+                best = side == 0 ? fmax(best, v64) : fmin(best, v64);
+                if (nc == 0) c0 = i;
+                if (nc == 1) c1 = i;
+                ++nc;
+            }
+        }
+    }
+    first = INT64_MAX;
+    inband = 0;
+    s_first = 0.0;
+    auto band = [&](int64_t i) {
+        const double v64 = pair_val(F.ps64 + 4 * i, q, side);
+        if (side == 0 ? (v64 >= best - F.tie) : (v64 <= best + F.tie)) {
+            ++inband;
+            const int64_t oi = F.sperm[i];
+            if (oi < first) {
+                first = oi;
+                s_first = F.ps64[4 * i + 3];
+            }
+        }
+    };
+    if (nc <= 2) {
+        if (nc > 0) band(c0);
+        if (nc > 1) band(c1);
+        return;
+    }
+    for (uint32_t e = 0; e < cnt; ++e) {
+        const float v = lv[side][e][lq];
+        if (!(side == 0 ? (v >= run - eps) : (v <= run + eps))) continue;
+        const int64_t base = (int64_t)lt[side][e][lq] * TILE;
+        const int len = (int)min((int64_t)TILE, n - base);
+        for (int j = 0; j < len; ++j)
+            if (near32(ps[base + j], qf, side, run, eps)) band(base + j);
     }
 }
 
@@ -553,7 +687,7 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
                                                           const double *__restrict__ queries,
                                                           const int32_t *__restrict__ qperm, int64_t m,
                                                           const Extent *__restrict__ ext, SweepOut<float> o,
-                                                          unsigned long long *__restrict__ skipped) {
+                                                          unsigned long long *__restrict__ skipped, Fused F) {
     // a tile is either near (raw samples (x, y, z, s)) or far ((-2 a, |a|^2) with
     // a = p - c, values apart): the two layouts share one LDS array
     __shared__ float4 tilebuf[TILE];
@@ -763,26 +897,39 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
         const int vl = (int)min((int64_t)64, max((int64_t)0, m - ((int64_t)blockIdx.x * MQ + 64 * w)));
         if (lane == 0 && nskip) atomicAdd(skipped, (unsigned long long)nskip * (unsigned long long)(vl * TILE));
     }
-    // lists and extremes leave in sorted order (slot sq), contiguous per work-group
+    // Resolve here, one lane per query, unless a list overflowed: then the
+    // lists and extremes leave in sorted order (slot sq) for resolve_list_kernel.
     if (valid) {
-        o.run[2 * sq] = run_lo;
-        o.run[2 * sq + 1] = run_hi;
-        for (int side = 0; side < 2; ++side) {
-            const uint32_t c = side == 0 ? clo : chi;
-            const float run = side == 0 ? run_lo : run_hi;
-            // entries noted before the extreme settled may have left its band: drop them
-            uint32_t k = 0;
-            if (!(c & OVERFLOW_BIT)) {
-                for (uint32_t e = 0; e < c; ++e) {
-                    const float v = lval[side][e][tid];
-                    if (side == 0 ? (v >= run - eps) : (v <= run + eps)) {
-                        o.tiles[(sq * 2 + side) * LIST + k] = ltile[side][e][tid];
-                        o.vals[(sq * 2 + side) * LIST + k] = v;
-                        ++k;
+        if (((clo | chi) & OVERFLOW_BIT) == 0) {
+            const float qf[3] = {qx, qy, qz};
+            const double q[3] = {queries[3 * qi], queries[3 * qi + 1], queries[3 * qi + 2]};
+            double lo, hi, s_a, s_b;
+            int64_t a, b;
+            int ta, tb;
+            resolve_lane(0, qf, q, run_lo, eps, clo, tid, ltile, lval, ps, n, F, lo, a, ta, s_a);
+            resolve_lane(1, qf, q, run_hi, eps, chi, tid, ltile, lval, ps, n, F, hi, b, tb, s_b);
+            write_query(qi, lo, hi, a, b, ta, tb, s_a, s_b, n, F.tol, F.tie, F.out);
+        } else {
+            o.run[2 * sq] = run_lo;
+            o.run[2 * sq + 1] = run_hi;
+            for (int side = 0; side < 2; ++side) {
+                const uint32_t c = side == 0 ? clo : chi;
+                const float run = side == 0 ? run_lo : run_hi;
+                // entries noted before the extreme settled may have left its band: drop them
+                uint32_t k = 0;
+                if (!(c & OVERFLOW_BIT)) {
+                    for (uint32_t e = 0; e < c; ++e) {
+                        const float v = lval[side][e][tid];
+                        if (side == 0 ? (v >= run - eps) : (v <= run + eps)) {
+                            o.tiles[(sq * 2 + side) * LIST + k] = ltile[side][e][tid];
+                            o.vals[(sq * 2 + side) * LIST + k] = v;
+                            ++k;
+                        }
                     }
                 }
+                o.count[2 * sq + side] = (c & OVERFLOW_BIT) ? c : k;
             }
-            o.count[2 * sq + side] = (c & OVERFLOW_BIT) ? c : k;
+            F.ovf_list[atomicAdd(F.ovf_len, 1ull)] = (int32_t)sq;
         }
     }
 }
@@ -794,6 +941,8 @@ struct SortedBufs {
     uint32_t *keys_in, *keys_out;
     int32_t *idx_in, *sperm, *qperm;
     float4 *ps, *tbox;
+    double *ps64;
+    int32_t *ovf_list;
     void *cub;
     size_t cub_bytes;
 };
@@ -816,6 +965,8 @@ SortedBufs carve_sorted(Carver &c, int64_t n, int64_t m) {
     b.sperm = c.take<int32_t>(n);
     b.qperm = c.take<int32_t>(m);
     b.ps = c.take<float4>(n);
+    b.ps64 = c.take<double>(4 * n);
+    b.ovf_list = c.take<int32_t>(m);
     b.tbox = c.take<float4>(2 * ((n + TILE - 1) / TILE));
     b.cub_bytes = std::max(cub_sort_bytes(n), cub_sort_bytes(m));
     b.cub = c.take<char>(b.cub_bytes);
@@ -826,7 +977,7 @@ template <typename T>
 struct SweepBufs {
     SweepOut<T> o;
     Pt4<T> *pts;
-    int64_t *overflows;  // [0] list overflows, [1] pairs the sorted sweep skipped
+    int64_t *overflows;  // [0] list overflows, [1] pairs the sorted sweep skipped, [2] its overflowed slots
 };
 
 template <typename T>
@@ -837,7 +988,7 @@ SweepBufs<T> carve_sweep(Carver &c, int64_t n, int64_t m) {
     b.o.count = c.take<uint32_t>(2 * m);
     b.o.tiles = c.take<int32_t>(2 * m * LIST);
     b.o.vals = c.take<T>(2 * m * LIST);
-    b.overflows = c.take<int64_t>(2);
+    b.overflows = c.take<int64_t>(3);
     return b;
 }
 
@@ -857,7 +1008,7 @@ sdfi_status launch(const double *samples, int64_t n, const double *queries, int6
     } else {
         pts = reinterpret_cast<const Pt4<T> *>(samples);
     }
-    SDFI_HIP(hipMemsetAsync(b.overflows, 0, 2 * sizeof(int64_t), st));
+    SDFI_HIP(hipMemsetAsync(b.overflows, 0, 3 * sizeof(int64_t), st));
     const int64_t per = (int64_t)BT * QPT;
     KernelTimer t1("sweep", st);
     sweep_kernel<T, QPT><<<(unsigned)((m + per - 1) / per), BT, 0, st>>>(pts, (int)n, queries, m, eps, b.o);
@@ -865,8 +1016,8 @@ sdfi_status launch(const double *samples, int64_t n, const double *queries, int6
     SDFI_HIP(hipGetLastError());
     KernelTimer t2("resolve", st);
     resolve_kernel<T><<<(unsigned)((m + 3) / 4), 256, 0, st>>>(samples, n, queries, m, eps, b.o, opt.tol,
-                                                                opt.tie_tol, lo, hi, argmax, argmin, flags,
-                                                                b.overflows, nullptr, nullptr, nullptr, nullptr);
+                                                                opt.tie_tol, BoundsOut{lo, hi, argmax, argmin, flags},
+                                                                b.overflows);
     t2.stop();
     SDFI_HIP(hipGetLastError());
     if (overflow_count) {
@@ -890,25 +1041,32 @@ sdfi_status launch_sorted(const double *samples, int64_t n, const double *querie
     morton_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(samples, 4, n, sb.ext, sb.keys_in, sb.idx_in);
     SDFI_HIP(hipcub::DeviceRadixSort::SortPairs(sb.cub, sb.cub_bytes, sb.keys_in, sb.keys_out, sb.idx_in, sb.sperm,
                                                 (int)n, 0, 30, st));
-    pack_sorted_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(samples, sb.sperm, n, sb.ps);
+    pack_sorted_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(samples, sb.sperm, n, sb.ps, sb.ps64);
     tile_box_kernel<<<(unsigned)((n + TILE - 1) / TILE), TILE, 0, st>>>(sb.ps, n, sb.tbox);
     morton_kernel<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(queries, 3, m, sb.ext, sb.keys_in, sb.idx_in);
     SDFI_HIP(hipcub::DeviceRadixSort::SortPairs(sb.cub, sb.cub_bytes, sb.keys_in, sb.keys_out, sb.idx_in, sb.qperm,
                                                 (int)m, 0, 30, st));
     SDFI_HIP(hipGetLastError());
-    SDFI_HIP(hipMemsetAsync(b.overflows, 0, 2 * sizeof(int64_t), st));
+    SDFI_HIP(hipMemsetAsync(b.overflows, 0, 3 * sizeof(int64_t), st));
+    const BoundsOut out{lo, hi, argmax, argmin, flags};
+    const Fused fused{sb.ps64, sb.sperm, opt.tol, opt.tie_tol, out, sb.ovf_list,
+                      reinterpret_cast<unsigned long long *>(b.overflows + 2)};
     KernelTimer t1("sweep", st);
     sweep_sorted_kernel<<<(unsigned)((m + MQ - 1) / MQ), MQ, 0, st>>>(sb.ps, (int)n, sb.tbox, queries, sb.qperm, m,
                                                                        sb.ext, b.o,
-                                                                       reinterpret_cast<unsigned long long *>(b.overflows + 1));
+                                                                       reinterpret_cast<unsigned long long *>(b.overflows + 1),
+                                                                       fused);
     t1.stop();
     note_count("sweep_pairs_skipped", b.overflows + 1, st);
     SDFI_HIP(hipGetLastError());
+    // the queries whose candidate lists overflowed (usually none)
     KernelTimer t2("resolve", st);
-    resolve_kernel<float><<<(unsigned)((m + 3) / 4), 256, 0, st>>>(samples, n, queries, m, 0.0f, b.o, opt.tol,
-                                                                    opt.tie_tol, lo, hi, argmax, argmin, flags,
-                                                                    b.overflows, sb.sperm, &sb.ext->eps, sb.qperm, sb.ps);
+    resolve_list_kernel<<<RESOLVE_LIST_BLOCKS, 256, 0, st>>>(samples, n, queries, &sb.ext->eps, b.o, opt.tol,
+                                                             opt.tie_tol, out, b.overflows, sb.ovf_list,
+                                                             reinterpret_cast<const unsigned long long *>(b.overflows + 2),
+                                                             sb.sperm, sb.qperm, sb.ps, sb.tbox);
     t2.stop();
+    note_count("bounds_list_overflows", b.overflows, st);
     SDFI_HIP(hipGetLastError());
     if (overflow_count) {
         SDFI_HIP(hipMemcpyAsync(overflow_count, b.overflows, sizeof(int64_t), hipMemcpyDeviceToHost, st));
