@@ -45,6 +45,7 @@ namespace {
 constexpr int BT = 256;    // threads per sweep work-group
 constexpr int TILE = 256;  // samples per LDS tile
 constexpr int LIST = 8;    // candidate tiles kept per query and side
+constexpr int BLK = 16;    // samples per block (one 16-row slice of a tile's matrix product)
 constexpr uint32_t OVERFLOW_BIT = 0x80000000u;
 
 template <typename T>
@@ -597,16 +598,28 @@ struct Fused {
 // kept tiles are screened again.
 __device__ inline void resolve_lane(int side, const float *qf, const double *q, float run, float eps, uint32_t cnt,
                                     int lq, const int32_t (*lt)[LIST][256], const float (*lv)[LIST][256],
-                                    const float4 *__restrict__ ps, int64_t n, const Fused &F, double &best,
-                                    int64_t &first, int &inband, double &s_first) {
+                                    const float4 *__restrict__ ps, const float4 *__restrict__ bbox, int64_t n,
+                                    const Fused &F, double &best, int64_t &first, int &inband, double &s_first) {
     best = side == 0 ? -INFINITY : INFINITY;
     int nc = 0;
     int64_t c0 = 0, c1 = 0;
     for (uint32_t e = 0; e < cnt; ++e) {
         const float v = lv[side][e][lq];
         if (!(side == 0 ? (v >= run - eps) : (v <= run + eps))) continue;
-        const int64_t base = (int64_t)lt[side][e][lq] * TILE;
-        const int len = (int)min((int64_t)TILE, n - base);
+        const int64_t tb = (int64_t)lt[side][e][lq] * TILE;
+        const int tlen = (int)min((int64_t)TILE, n - tb);
+        for (int bk = 0; bk * BLK < tlen; ++bk) {
+            // a block whose box and value range keep every pair with q out of
+            // the screen's band is skipped (it holds no survivor)
+            const int64_t k = tb / BLK + bk;
+            const float4 bl = bbox[2 * k], bh = bbox[2 * k + 1];
+            const float gx = fmaxf(0.0f, fmaxf(bl.x - qf[0], qf[0] - bh.x));
+            const float gy = fmaxf(0.0f, fmaxf(bl.y - qf[1], qf[1] - bh.y));
+            const float gz = fmaxf(0.0f, fmaxf(bl.z - qf[2], qf[2] - bh.z));
+            const float g = sqrtf(gx * gx + gy * gy + gz * gz) * (1.0f - 8.0f * 5.9604645e-8f);
+            if (side == 0 ? (bh.w - g < run - 2.0f * eps) : (bl.w + g > run + 2.0f * eps)) continue;
+            const int64_t base = tb + bk * BLK;
+            const int len = (int)min((int64_t)BLK, n - base);
         for (int j0 = 0; j0 < len; j0 += 4) {
             float4 p4[4];  // four loads in flight
 #pragma unroll
@@ -621,6 +634,7 @@ __device__ inline void resolve_lane(int side, const float *qf, const double *q, 
                 if (nc == 1) c1 = i;
                 ++nc;
             }
+        }
         }
     }
     first = INT64_MAX;
@@ -678,6 +692,35 @@ __global__ __launch_bounds__(TILE) void tile_box_kernel(const float4 *__restrict
     }
 }
 
+// box and value range of each block of BLK sorted samples, laid out like tbox
+__global__ void block_box_kernel(const float4 *__restrict__ ps, int64_t n, float4 *bbox) {
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k * BLK >= n) return;
+    float4 lo = make_float4(INFINITY, INFINITY, INFINITY, INFINITY);
+    float4 hi = make_float4(-INFINITY, -INFINITY, -INFINITY, -INFINITY);
+    const int cnt = (int)min((int64_t)BLK, n - k * BLK);
+    for (int j = 0; j < cnt; ++j) {
+        const float4 p = ps[k * BLK + j];
+        lo = make_float4(fminf(lo.x, p.x), fminf(lo.y, p.y), fminf(lo.z, p.z), fminf(lo.w, p.w));
+        hi = make_float4(fmaxf(hi.x, p.x), fmaxf(hi.y, p.y), fmaxf(hi.z, p.z), fmaxf(hi.w, p.w));
+    }
+    bbox[2 * k] = lo;
+    bbox[2 * k + 1] = hi;
+}
+
+// Can a pair of a point in box [ql, qh] with a sample of the box/range
+// (bl, bh) have s - d >= lo - 2 eps or s + d <= hi + 2 eps?  False only when
+// every such pair is below lo - 2 eps and above hi + 2 eps (the gap is taken
+// a few float32 roundings short, so the test errs towards true).
+__device__ inline bool box_reach(const float *ql, const float *qh, float4 bl, float4 bh, float lo, float hi,
+                                 float eps) {
+    const float gx = fmaxf(0.0f, fmaxf(bl.x - qh[0], ql[0] - bh.x));
+    const float gy = fmaxf(0.0f, fmaxf(bl.y - qh[1], ql[1] - bh.y));
+    const float gz = fmaxf(0.0f, fmaxf(bl.z - qh[2], ql[2] - bh.z));
+    const float g = sqrtf(gx * gx + gy * gy + gz * gz) * (1.0f - 8.0f * 5.9604645e-8f);
+    return !((bh.w - g < lo - 2.0f * eps) && (bl.w + g > hi + 2.0f * eps));
+}
+
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // One work-group: 256 consecutive queries of the sorted order (lane l of
@@ -687,7 +730,8 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
                                                           const double *__restrict__ queries,
                                                           const int32_t *__restrict__ qperm, int64_t m,
                                                           const Extent *__restrict__ ext, SweepOut<float> o,
-                                                          unsigned long long *__restrict__ skipped, Fused F) {
+                                                          unsigned long long *__restrict__ skipped, Fused F,
+                                                          const float4 *__restrict__ bbox) {
     // a tile is either near (raw samples (x, y, z, s)) or far ((-2 a, |a|^2) with
     // a = p - c, values apart): the two layouts share one LDS array
     __shared__ float4 tilebuf[TILE];
@@ -740,7 +784,14 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
     uint32_t clo = 0, chi = 0;
     const int ntiles = (n + TILE - 1) / TILE;
     float wlo_all = -INFINITY, whi_all = INFINITY;  // the wavefront's lowest / highest running extremes
-    unsigned nskip = 0;  // far tiles this wavefront skipped
+    // valid queries of this wavefront (stand-in lanes past m are not counted)
+    const int vl = (int)min((int64_t)64, max((int64_t)0, m - ((int64_t)blockIdx.x * MQ + 64 * w)));
+    unsigned long long nskipped = 0;  // query x sample pairs this wavefront ruled out
+    float wql[3], wqh[3];             // this wavefront's query box
+    for (int k = 0; k < 3; ++k) {
+        wql[k] = wbox[w][k];
+        wqh[k] = wbox[w][3 + k];
+    }
     int phase = 0;       // alternates per chunk, so that need masks are not rewritten before all waves read them
     // One tile: stage it in LDS, reduce it (the matrix path for far tiles, the
     // direct formula for near ones), note it in the candidate lists.  `act`:
@@ -748,6 +799,18 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
     // Called with the same (t, far) by all wavefronts of the work-group.
     auto sweep_tile = [&](int t, bool far, bool act) {
         const int cnt = min(TILE, n - t * TILE);
+        // blocks of a far tile this wavefront needs: one test per lane, the
+        // tile test at block size
+        unsigned long long bneed = 0;
+        if (far && act) {
+            bool nb = false;
+            if (lane < TILE / BLK) {
+                const int64_t k = (int64_t)t * (TILE / BLK) + lane;
+                nb = box_reach(wql, wqh, bbox[2 * k], bbox[2 * k + 1], wlo_all, whi_all, eps);
+            }
+            bneed = __ballot(nb);
+            nskipped += (unsigned long long)(TILE / BLK - __popcll(bneed)) * BLK * vl;
+        }
         __syncthreads();
         if (tid < cnt) {
             const float4 p = ps[(int64_t)t * TILE + tid];
@@ -778,7 +841,8 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
             float hi4[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
             const float *cenf = reinterpret_cast<const float *>(cen);
 #pragma unroll 2
-            for (int b = 0; b < TILE / 16; ++b) {
+            for (unsigned long long bm = bneed; bm; bm &= bm - 1) {
+                const int b = __builtin_ctzll(bm);
                 // A[i][k]: sample 16 b + i, component k (this lane: i = lane & 15, k = lane >> 4)
                 const float a = cenf[4 * (16 * b + (lane & 15)) + (lane >> 4)];
                 // rows of the product held by this lane: samples 16 b + 4 (lane >> 4) + 0..3
@@ -872,7 +936,7 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
             const unsigned long long mine = __ballot(need);
             unsigned long long todo = inpass;
             if (pass == 1) {
-                nskip += (unsigned)__popcll(inpass & ~mine);
+                nskipped += (unsigned long long)__popcll(inpass & ~mine) * TILE * vl;
                 if (lane == 0) wneed[phase][w] = mine;
                 __syncthreads();
                 todo = wneed[phase][0] | wneed[phase][1] | wneed[phase][2] | wneed[phase][3];
@@ -893,10 +957,7 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
         }
     }
     // pairs ruled out without evaluation (stand-in lanes past m not counted)
-    {
-        const int vl = (int)min((int64_t)64, max((int64_t)0, m - ((int64_t)blockIdx.x * MQ + 64 * w)));
-        if (lane == 0 && nskip) atomicAdd(skipped, (unsigned long long)nskip * (unsigned long long)(vl * TILE));
-    }
+    if (lane == 0 && nskipped) atomicAdd(skipped, nskipped);
     // Resolve here, one lane per query, unless a list overflowed: then the
     // lists and extremes leave in sorted order (slot sq) for resolve_list_kernel.
     if (valid) {
@@ -906,8 +967,8 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
             double lo, hi, s_a, s_b;
             int64_t a, b;
             int ta, tb;
-            resolve_lane(0, qf, q, run_lo, eps, clo, tid, ltile, lval, ps, n, F, lo, a, ta, s_a);
-            resolve_lane(1, qf, q, run_hi, eps, chi, tid, ltile, lval, ps, n, F, hi, b, tb, s_b);
+            resolve_lane(0, qf, q, run_lo, eps, clo, tid, ltile, lval, ps, bbox, n, F, lo, a, ta, s_a);
+            resolve_lane(1, qf, q, run_hi, eps, chi, tid, ltile, lval, ps, bbox, n, F, hi, b, tb, s_b);
             write_query(qi, lo, hi, a, b, ta, tb, s_a, s_b, n, F.tol, F.tie, F.out);
         } else {
             o.run[2 * sq] = run_lo;
@@ -940,7 +1001,7 @@ struct SortedBufs {
     Extent *ext;
     uint32_t *keys_in, *keys_out;
     int32_t *idx_in, *sperm, *qperm;
-    float4 *ps, *tbox;
+    float4 *ps, *tbox, *bbox;
     double *ps64;
     int32_t *ovf_list;
     void *cub;
@@ -968,6 +1029,7 @@ SortedBufs carve_sorted(Carver &c, int64_t n, int64_t m) {
     b.ps64 = c.take<double>(4 * n);
     b.ovf_list = c.take<int32_t>(m);
     b.tbox = c.take<float4>(2 * ((n + TILE - 1) / TILE));
+    b.bbox = c.take<float4>(2 * ((n + BLK - 1) / BLK));
     b.cub_bytes = std::max(cub_sort_bytes(n), cub_sort_bytes(m));
     b.cub = c.take<char>(b.cub_bytes);
     return b;
@@ -1043,6 +1105,7 @@ sdfi_status launch_sorted(const double *samples, int64_t n, const double *querie
                                                 (int)n, 0, 30, st));
     pack_sorted_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(samples, sb.sperm, n, sb.ps, sb.ps64);
     tile_box_kernel<<<(unsigned)((n + TILE - 1) / TILE), TILE, 0, st>>>(sb.ps, n, sb.tbox);
+    block_box_kernel<<<(unsigned)(((n + BLK - 1) / BLK + 255) / 256), 256, 0, st>>>(sb.ps, n, sb.bbox);
     morton_kernel<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(queries, 3, m, sb.ext, sb.keys_in, sb.idx_in);
     SDFI_HIP(hipcub::DeviceRadixSort::SortPairs(sb.cub, sb.cub_bytes, sb.keys_in, sb.keys_out, sb.idx_in, sb.qperm,
                                                 (int)m, 0, 30, st));
@@ -1055,7 +1118,7 @@ sdfi_status launch_sorted(const double *samples, int64_t n, const double *querie
     sweep_sorted_kernel<<<(unsigned)((m + MQ - 1) / MQ), MQ, 0, st>>>(sb.ps, (int)n, sb.tbox, queries, sb.qperm, m,
                                                                        sb.ext, b.o,
                                                                        reinterpret_cast<unsigned long long *>(b.overflows + 1),
-                                                                       fused);
+                                                                       fused, sb.bbox);
     t1.stop();
     note_count("sweep_pairs_skipped", b.overflows + 1, st);
     SDFI_HIP(hipGetLastError());
