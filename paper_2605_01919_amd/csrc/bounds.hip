@@ -810,6 +810,19 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
             }
             bneed = __ballot(nb);
             nskipped += (unsigned long long)(TILE / BLK - __popcll(bneed)) * BLK * vl;
+        } else if (!far) {
+            // the same for a near tile (possibly the short last one), against
+            // the extremes as they stand
+            const int nblk = (cnt + BLK - 1) / BLK;
+            bool nb = false;
+            if (lane < nblk) {
+                const int64_t k = (int64_t)t * (TILE / BLK) + lane;
+                nb = box_reach(wql, wqh, bbox[2 * k], bbox[2 * k + 1], wlo_all, whi_all, eps);
+            }
+            bneed = __ballot(nb);
+            int used = __popcll(bneed) * BLK;
+            if ((bneed >> (nblk - 1)) & 1ull) used -= nblk * BLK - cnt;
+            nskipped += (unsigned long long)(cnt - used) * vl;
         }
         __syncthreads();
         if (tid < cnt) {
@@ -887,16 +900,23 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
             tlo = mine == 0 ? lo4[0] : (mine == 1 ? lo4[1] : (mine == 2 ? lo4[2] : lo4[3]));
             thi = mine == 0 ? hi4[0] : (mine == 1 ? hi4[1] : (mine == 2 ? hi4[2] : hi4[3]));
         } else if (!far) {
-            for (int j = 0; j < cnt; ++j) {
-                const float4 p = raw[j];
-                const float dx = qx - p.x, dy = qy - p.y, dz = qz - p.z;
-                const float d = __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz);
-                tlo = fmaxf(tlo, p.w - d);
-                thi = fminf(thi, p.w + d);
+            for (unsigned long long bm = bneed; bm; bm &= bm - 1) {
+                const int j0 = __builtin_ctzll(bm) * BLK, j1 = min(j0 + BLK, cnt);
+                for (int j = j0; j < j1; ++j) {
+                    const float4 p = raw[j];
+                    const float dx = qx - p.x, dy = qy - p.y, dz = qz - p.z;
+                    const float d = __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz);
+                    tlo = fmaxf(tlo, p.w - d);
+                    thi = fminf(thi, p.w + d);
+                }
             }
         }
         note_tile_lds(0, tid, t, tlo, run_lo, clo, eps, ltile, lval);
         note_tile_lds(1, tid, t, thi, run_hi, chi, eps, ltile, lval);
+        if (!far) {  // the near tiles settle the extremes: keep the block test current
+            wlo_all = wred_min(run_lo);
+            whi_all = wred_max(run_hi);
+        }
     };
     // Two passes over the tiles: the near ones first (direct formula), so that
     // the running extremes are already close to final when the far tiles are
@@ -909,7 +929,10 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
     // queries and the tile, when smax - g and smin + g clear those.  Such pairs
     // can neither move an extreme nor enter its band (the same margin as the
     // group test), so the results are those of the full sweep.  The work-group
-    // stages only the tiles that one of its wavefronts needs.
+    // stages only the tiles that one of its wavefronts needs, and a wavefront
+    // reduces only the blocks of BLK samples that pass the same test at block
+    // size (near tiles included, against the extremes as they stand: the
+    // first near tiles are reduced whole).
     for (int pass = 0; pass < 2; ++pass) {
         for (int c0 = 0; c0 < ntiles; c0 += 64) {
             const int t = c0 + lane;
