@@ -596,28 +596,41 @@ struct Fused {
 // extreme, the band's population and that sample's value follow.  The first
 // two survivors are kept in registers for the band count; with more, the
 // kept tiles are screened again.
+// List entries are tile indices, or with `packed` tile | (block mask << 16):
+// the blocks of BLK samples that can hold a survivor.
+__device__ inline int64_t entry_tile(int32_t ent, bool packed) { return packed ? (ent & 0xFFFF) : ent; }
+__device__ inline uint32_t entry_blocks(int32_t ent, bool packed) {
+    return packed ? ((uint32_t)ent >> 16) : 0xFFFFu;
+}
+
 __device__ inline void resolve_lane(int side, const float *qf, const double *q, float run, float eps, uint32_t cnt,
                                     int lq, const int32_t (*lt)[LIST][256], const float (*lv)[LIST][256],
-                                    const float4 *__restrict__ ps, const float4 *__restrict__ bbox, int64_t n,
-                                    const Fused &F, double &best, int64_t &first, int &inband, double &s_first) {
+                                    bool packed, const float4 *__restrict__ ps, const float4 *__restrict__ bbox,
+                                    int64_t n, const Fused &F, double &best, int64_t &first, int &inband,
+                                    double &s_first) {
     best = side == 0 ? -INFINITY : INFINITY;
     int nc = 0;
     int64_t c0 = 0, c1 = 0;
     for (uint32_t e = 0; e < cnt; ++e) {
         const float v = lv[side][e][lq];
         if (!(side == 0 ? (v >= run - eps) : (v <= run + eps))) continue;
-        const int64_t tb = (int64_t)lt[side][e][lq] * TILE;
+        const int32_t ent = lt[side][e][lq];
+        const int64_t tb = entry_tile(ent, packed) * TILE;
         const int tlen = (int)min((int64_t)TILE, n - tb);
-        for (int bk = 0; bk * BLK < tlen; ++bk) {
-            // a block whose box and value range keep every pair with q out of
-            // the screen's band is skipped (it holds no survivor)
-            const int64_t k = tb / BLK + bk;
-            const float4 bl = bbox[2 * k], bh = bbox[2 * k + 1];
-            const float gx = fmaxf(0.0f, fmaxf(bl.x - qf[0], qf[0] - bh.x));
-            const float gy = fmaxf(0.0f, fmaxf(bl.y - qf[1], qf[1] - bh.y));
-            const float gz = fmaxf(0.0f, fmaxf(bl.z - qf[2], qf[2] - bh.z));
-            const float g = sqrtf(gx * gx + gy * gy + gz * gz) * (1.0f - 8.0f * 5.9604645e-8f);
-            if (side == 0 ? (bh.w - g < run - 2.0f * eps) : (bl.w + g > run + 2.0f * eps)) continue;
+        for (uint32_t bm = entry_blocks(ent, packed) & ((1u << ((tlen + BLK - 1) / BLK)) - 1u); bm; bm &= bm - 1) {
+            const int bk = __builtin_ctz(bm);
+            if (!packed) {
+                // without the sweep's block mask: a block whose box and value
+                // range keep every pair with q out of the screen's band is
+                // skipped (it holds no survivor)
+                const int64_t k = tb / BLK + bk;
+                const float4 bl = bbox[2 * k], bh = bbox[2 * k + 1];
+                const float gx = fmaxf(0.0f, fmaxf(bl.x - qf[0], qf[0] - bh.x));
+                const float gy = fmaxf(0.0f, fmaxf(bl.y - qf[1], qf[1] - bh.y));
+                const float gz = fmaxf(0.0f, fmaxf(bl.z - qf[2], qf[2] - bh.z));
+                const float g = sqrtf(gx * gx + gy * gy + gz * gz) * (1.0f - 8.0f * 5.9604645e-8f);
+                if (side == 0 ? (bh.w - g < run - 2.0f * eps) : (bl.w + g > run + 2.0f * eps)) continue;
+            }
             const int64_t base = tb + bk * BLK;
             const int len = (int)min((int64_t)BLK, n - base);
         for (int j0 = 0; j0 < len; j0 += 4) {
@@ -659,7 +672,7 @@ __device__ inline void resolve_lane(int side, const float *qf, const double *q, 
     for (uint32_t e = 0; e < cnt; ++e) {
         const float v = lv[side][e][lq];
         if (!(side == 0 ? (v >= run - eps) : (v <= run + eps))) continue;
-        const int64_t base = (int64_t)lt[side][e][lq] * TILE;
+        const int64_t base = entry_tile(lt[side][e][lq], packed) * TILE;
         const int len = (int)min((int64_t)TILE, n - base);
         for (int j = 0; j < len; ++j)
             if (near32(ps[base + j], qf, side, run, eps)) band(base + j);
@@ -784,6 +797,9 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
     uint32_t clo = 0, chi = 0;
     const int ntiles = (n + TILE - 1) / TILE;
     float wlo_all = -INFINITY, whi_all = INFINITY;  // the wavefront's lowest / highest running extremes
+    // list entries carry a mask of the tile's blocks that can hold a sample of
+    // the final band (packed with the tile index when that fits 16 bits)
+    const bool packed = ntiles <= 65536;
     // valid queries of this wavefront (stand-in lanes past m are not counted)
     const int vl = (int)min((int64_t)64, max((int64_t)0, m - ((int64_t)blockIdx.x * MQ + 64 * w)));
     unsigned long long nskipped = 0;  // query x sample pairs this wavefront ruled out
@@ -837,6 +853,10 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
         }
         __syncthreads();
         float tlo = -INFINITY, thi = INFINITY;
+        // blocks that can hold a sample within 2 eps of this tile's extreme for
+        // this lane's query (a superset: the final screen keeps only samples
+        // within eps of the final extreme, which is at least the tile's)
+        uint32_t mlo = 0, mhi = 0;
         if (far && act) {
             // Running extremes of the four query columns this lane holds, widened
             // by 2 eps.  A pair with d >= max(s - rl, rh - s) has s - d <= rl and
@@ -874,6 +894,10 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
                     need |= dmin2 < T * T;
                 }
                 if (__any(need)) {
+                    // a block the group test passes over holds no sample of
+                    // either band; the computed ones are kept for both sides
+                    mlo |= 1u << b;
+                    mhi |= 1u << b;
 #pragma unroll
                     for (int cb = 0; cb < 4; ++cb) {
                         const float d0 = __builtin_amdgcn_sqrtf(fabsf(D[cb][0]));
@@ -901,18 +925,25 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
             thi = mine == 0 ? hi4[0] : (mine == 1 ? hi4[1] : (mine == 2 ? hi4[2] : hi4[3]));
         } else if (!far) {
             for (unsigned long long bm = bneed; bm; bm &= bm - 1) {
-                const int j0 = __builtin_ctzll(bm) * BLK, j1 = min(j0 + BLK, cnt);
+                const int bk = __builtin_ctzll(bm);
+                const int j0 = bk * BLK, j1 = min(j0 + BLK, cnt);
+                float blo = -INFINITY, bhi = INFINITY;
                 for (int j = j0; j < j1; ++j) {
                     const float4 p = raw[j];
                     const float dx = qx - p.x, dy = qy - p.y, dz = qz - p.z;
                     const float d = __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz);
-                    tlo = fmaxf(tlo, p.w - d);
-                    thi = fminf(thi, p.w + d);
+                    blo = fmaxf(blo, p.w - d);
+                    bhi = fminf(bhi, p.w + d);
                 }
+                // bits set against the tile extreme so far stay valid as it grows
+                tlo = fmaxf(tlo, blo);
+                thi = fminf(thi, bhi);
+                if (blo >= tlo - 2.0f * eps) mlo |= 1u << bk;
+                if (bhi <= thi + 2.0f * eps) mhi |= 1u << bk;
             }
         }
-        note_tile_lds(0, tid, t, tlo, run_lo, clo, eps, ltile, lval);
-        note_tile_lds(1, tid, t, thi, run_hi, chi, eps, ltile, lval);
+        note_tile_lds(0, tid, packed ? (t | (int)(mlo << 16)) : t, tlo, run_lo, clo, eps, ltile, lval);
+        note_tile_lds(1, tid, packed ? (t | (int)(mhi << 16)) : t, thi, run_hi, chi, eps, ltile, lval);
         if (!far) {  // the near tiles settle the extremes: keep the block test current
             wlo_all = wred_min(run_lo);
             whi_all = wred_max(run_hi);
@@ -990,8 +1021,8 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
             double lo, hi, s_a, s_b;
             int64_t a, b;
             int ta, tb;
-            resolve_lane(0, qf, q, run_lo, eps, clo, tid, ltile, lval, ps, bbox, n, F, lo, a, ta, s_a);
-            resolve_lane(1, qf, q, run_hi, eps, chi, tid, ltile, lval, ps, bbox, n, F, hi, b, tb, s_b);
+            resolve_lane(0, qf, q, run_lo, eps, clo, tid, ltile, lval, packed, ps, bbox, n, F, lo, a, ta, s_a);
+            resolve_lane(1, qf, q, run_hi, eps, chi, tid, ltile, lval, packed, ps, bbox, n, F, hi, b, tb, s_b);
             write_query(qi, lo, hi, a, b, ta, tb, s_a, s_b, n, F.tol, F.tie, F.out);
         } else {
             o.run[2 * sq] = run_lo;
@@ -1005,7 +1036,7 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
                     for (uint32_t e = 0; e < c; ++e) {
                         const float v = lval[side][e][tid];
                         if (side == 0 ? (v >= run - eps) : (v <= run + eps)) {
-                            o.tiles[(sq * 2 + side) * LIST + k] = ltile[side][e][tid];
+                            o.tiles[(sq * 2 + side) * LIST + k] = (int32_t)entry_tile(ltile[side][e][tid], packed);
                             o.vals[(sq * 2 + side) * LIST + k] = v;
                             ++k;
                         }
