@@ -282,108 +282,52 @@ __device__ inline bool near32(float4 p, const float *qf, int side, float run, fl
     return side == 0 ? (p.w - d >= run - eps) : (p.w + d <= run + eps);
 }
 
-// One query, one wavefront: the lists in slot li.
-// sperm (nullable): tile t holds the samples sperm[t*TILE ...] (sorted order);
-// qperm (nullable): the lists of slot li belong to query qperm[li];
-// ps32 (nullable): float32 copy of the samples in tile order, for the screen;
-// tbox (nullable, with ps32): box and value range of each tile.
+// Float64 mode, one wavefront per query: the listed tiles (every tile after
+// an overflow) in float64, the exact extreme, the smallest index within the
+// tie band and the band's population.
 template <typename T>
-__device__ inline void resolve_slot(int64_t li, const double *__restrict__ samples, int64_t n,
-                                    const double *__restrict__ queries, T eps, const SweepOut<T> &o, double tol,
-                                    double tie, const BoundsOut &out, int64_t *overflows,
-                                    const int32_t *__restrict__ sperm, const int32_t *__restrict__ qperm,
-                                    const float4 *__restrict__ ps32, const float4 *__restrict__ tbox) {
+__global__ __launch_bounds__(256) void resolve_kernel(const double *__restrict__ samples, int64_t n,
+                                                      const double *__restrict__ queries, int64_t m, T eps,
+                                                      SweepOut<T> o, double tol, double tie, BoundsOut out,
+                                                      int64_t *overflows) {
+    const int64_t qi = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    if (qi >= m) return;
     const int lane = threadIdx.x & 63;
-    const int64_t qi = qperm ? (int64_t)qperm[li] : li;
-    // with the float32 copy (sorted like the tiles), a listed tile's samples go
-    // to float64 only when their float32 value is within eps of the float32
-    // extreme: every sample within the tie band of the float64 extreme is
-    const float qf[3] = {(float)queries[3 * qi], (float)queries[3 * qi + 1], (float)queries[3 * qi + 2]};
     const double q[3] = {queries[3 * qi], queries[3 * qi + 1], queries[3 * qi + 2]};
     double ext[2];
     int64_t arg[2];
     int tied[2];
     for (int side = 0; side < 2; ++side) {
-        uint32_t cnt = o.count[2 * li + side];
+        const uint32_t cnt = o.count[2 * qi + side];
         const bool full = (cnt & OVERFLOW_BIT) != 0;
-        const T run = o.run[2 * li + side];
-        const int64_t lb = (li * 2 + side) * LIST;
-        const int ntiles = (int)((n + TILE - 1) / TILE);
-        // Calls fn(t, e) for every tile t to look at: the kept entries e of the
-        // list, or after an overflow every tile (e = -1) that can hold a sample
-        // passing the float32 screen, by the tile's box and value range (the
-        // margin of the sweep's own tile test: a tile ruled out holds only
-        // samples the screen would drop, so the results do not change).
-        auto for_tiles = [&](auto &&fn) {
-            if (!full) {
-                for (int e = 0; e < (int)cnt; ++e) {
-                    T v = o.vals[lb + e];
-                    if (side == 0 ? (v >= run - eps) : (v <= run + eps)) fn(o.tiles[lb + e], e);
+        const T run = o.run[2 * qi + side];
+        const int64_t lb = (qi * 2 + side) * LIST;
+        const int nt = full ? (int)((n + TILE - 1) / TILE) : (int)cnt;
+        auto for_samples = [&](auto &&fn) {
+            for (int e = 0; e < nt; ++e) {
+                int t = e;
+                if (!full) {
+                    const T v = o.vals[lb + e];
+                    if (!(side == 0 ? (v >= run - eps) : (v <= run + eps))) continue;
+                    t = o.tiles[lb + e];
                 }
-            } else if (ps32 && tbox) {
-                for (int c0 = 0; c0 < ntiles; c0 += 64) {
-                    const int t = c0 + lane;
-                    bool reach = false;
-                    if (t < ntiles) {
-                        const float4 tl = tbox[2 * t], th = tbox[2 * t + 1];
-                        const float gx = fmaxf(0.0f, fmaxf(tl.x - qf[0], qf[0] - th.x));
-                        const float gy = fmaxf(0.0f, fmaxf(tl.y - qf[1], qf[1] - th.y));
-                        const float gz = fmaxf(0.0f, fmaxf(tl.z - qf[2], qf[2] - th.z));
-                        const float gap = sqrtf(gx * gx + gy * gy + gz * gz) * (1.0f - 8.0f * 5.9604645e-8f);
-                        reach = side == 0 ? !(th.w - gap < (float)run - 2.0f * (float)eps)
-                                          : !(tl.w + gap > (float)run + 2.0f * (float)eps);
-                    }
-                    for (unsigned long long mk = __ballot(reach); mk; mk &= mk - 1) fn(c0 + __builtin_ctzll(mk), -1);
+                for (int r = 0; r < TILE / 64; ++r) {
+                    const int64_t i = (int64_t)t * TILE + lane + 64 * r;
+                    if (i < n) fn(i, pair_val(samples + 4 * i, q, side));
                 }
-            } else {
-                for (int t = 0; t < ntiles; ++t) fn(t, -1);
             }
         };
-        // exact extreme over the candidate tiles (after an overflow the float32
-        // screen still holds, `run` being the extreme of every evaluated pair
-        // and the pairs ruled out lying below it); with a list (at most LIST
-        // tiles of TILE = 4 x 64 samples) bit 4 e + r of `pass` marks that
-        // sample lane + 64 r of entry e was evaluated, so that the band count
-        // below revisits only those
-        static_assert(LIST * (TILE / 64) <= 32, "one bit per lane sample of the listed tiles");
-        uint32_t pass = 0;
         double best = side == 0 ? -INFINITY : INFINITY;
-        for_tiles([&](int t, int e) {
-            for (int r = 0; r < TILE / 64; ++r) {
-                int64_t i = (int64_t)t * TILE + lane + 64 * r;
-                if (i < n && (!ps32 || near32(ps32[i], qf, side, (float)run, (float)eps))) {
-                    if (e >= 0 && ps32) pass |= 1u << (4 * e + r);
-                    const int64_t oi = sperm ? (int64_t)sperm[i] : i;
-                    double v = pair_val(samples + 4 * oi, q, side);
-                    best = side == 0 ? fmax(best, v) : fmin(best, v);
-                }
-            }
-        });
+        for_samples([&](int64_t, double v) { best = side == 0 ? fmax(best, v) : fmin(best, v); });
         best = side == 0 ? wave_max(best) : wave_min(best);
-        // smallest index within the tie band, and the band's population
         int64_t first = INT64_MAX;
         int inband = 0;
-        auto band = [&](int64_t i) {
-            const int64_t oi = sperm ? (int64_t)sperm[i] : i;
-            double v = pair_val(samples + 4 * oi, q, side);
+        for_samples([&](int64_t i, double v) {
             if (side == 0 ? (v >= best - tie) : (v <= best + tie)) {
-                inband++;
-                first = oi < first ? oi : first;
+                ++inband;
+                first = i < first ? i : first;
             }
-        };
-        if (!full && ps32) {
-            for (uint32_t b = pass; b; b &= b - 1) {
-                const int k = __builtin_ctz(b);
-                band((int64_t)o.tiles[lb + k / 4] * TILE + lane + 64 * (k % 4));
-            }
-        } else {
-            for_tiles([&](int t, int) {
-                for (int r = 0; r < TILE / 64; ++r) {
-                    int64_t i = (int64_t)t * TILE + lane + 64 * r;
-                    if (i < n && (!ps32 || near32(ps32[i], qf, side, (float)run, (float)eps))) band(i);
-                }
-            });
-        }
+        });
         ext[side] = best;
         arg[side] = wave_min_i64(first);
         tied[side] = wave_sum(inband);
@@ -396,35 +340,120 @@ __device__ inline void resolve_slot(int64_t li, const double *__restrict__ sampl
     }
 }
 
-// one wavefront per query slot
-template <typename T>
-__global__ __launch_bounds__(256) void resolve_kernel(const double *__restrict__ samples, int64_t n,
-                                                      const double *__restrict__ queries, int64_t m, T eps,
-                                                      SweepOut<T> o, double tol, double tie, BoundsOut out,
-                                                      int64_t *overflows) {
-    const int64_t li = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-    if (li >= m) return;
-    resolve_slot<T>(li, samples, n, queries, eps, o, tol, tie, out, overflows, nullptr, nullptr, nullptr, nullptr);
-}
+constexpr int RL_W = 16;  // wavefronts per query of the overflow resolve
 
-// the slots listed by the sorted sweep (queries whose candidate lists
-// overflowed): a fixed grid of wavefronts strides over the list, whose length
-// is read on the device (zero: every wavefront exits at once)
-__global__ __launch_bounds__(256) void resolve_list_kernel(const double *__restrict__ samples, int64_t n,
-                                                           const double *__restrict__ queries,
-                                                           const float *__restrict__ eps_dev, SweepOut<float> o,
-                                                           double tol, double tie, BoundsOut out,
-                                                           int64_t *overflows, const int32_t *__restrict__ list,
-                                                           const unsigned long long *__restrict__ list_len,
-                                                           const int32_t *__restrict__ sperm,
-                                                           const int32_t *__restrict__ qperm,
-                                                           const float4 *__restrict__ ps32,
-                                                           const float4 *__restrict__ tbox) {
+// The slots listed by the sorted sweep (queries whose candidate lists
+// overflowed), one work-group of RL_W wavefronts per query: the tiles of a
+// side (its list, or after an overflow every tile that can reach the band by
+// the tile test) are dealt out to the wavefronts, and the extreme, the
+// smallest index within the tie band and the band's population are reduced
+// over the work-group.  A fixed grid strides over the list, whose length is
+// read on the device (zero: every work-group exits at once).
+__global__ __launch_bounds__(RL_W * 64) void resolve_list_kernel(
+    const double *__restrict__ samples, int64_t n, const double *__restrict__ queries,
+    const float *__restrict__ eps_dev, SweepOut<float> o, double tol, double tie, BoundsOut out, int64_t *overflows,
+    const int32_t *__restrict__ list, const unsigned long long *__restrict__ list_len,
+    const int32_t *__restrict__ sperm, const int32_t *__restrict__ qperm, const float4 *__restrict__ ps32,
+    const float4 *__restrict__ tbox) {
+    __shared__ double rd[RL_W];
+    __shared__ int64_t ri[RL_W];
+    __shared__ int rc[RL_W];
     const int64_t len = (int64_t)*list_len;
     const float eps = *eps_dev;
-    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
-    for (int64_t k = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); k < len; k += waves)
-        resolve_slot<float>(list[k], samples, n, queries, eps, o, tol, tie, out, overflows, sperm, qperm, ps32, tbox);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int ntiles = (int)((n + TILE - 1) / TILE);
+    for (int64_t k = blockIdx.x; k < len; k += gridDim.x) {
+        const int64_t li = list[k];
+        const int64_t qi = qperm[li];
+        const float qf[3] = {(float)queries[3 * qi], (float)queries[3 * qi + 1], (float)queries[3 * qi + 2]};
+        const double q[3] = {queries[3 * qi], queries[3 * qi + 1], queries[3 * qi + 2]};
+        double ext[2];
+        int64_t arg[2];
+        int tied[2];
+        for (int side = 0; side < 2; ++side) {
+            const uint32_t cnt = o.count[2 * li + side];
+            const bool full = (cnt & OVERFLOW_BIT) != 0;
+            const float run = o.run[2 * li + side];
+            const int64_t lb = (li * 2 + side) * LIST;
+            // this wavefront's share of the side's tiles
+            auto for_tiles = [&](auto &&fn) {
+                if (!full) {
+                    for (int e = w; e < (int)cnt; e += RL_W) {
+                        const float v = o.vals[lb + e];
+                        if (side == 0 ? (v >= run - eps) : (v <= run + eps)) fn(o.tiles[lb + e]);
+                    }
+                } else {
+                    for (int c0 = 64 * w; c0 < ntiles; c0 += 64 * RL_W) {
+                        const int t = c0 + lane;
+                        bool reach = false;
+                        if (t < ntiles) {
+                            const float4 tl = tbox[2 * t], th = tbox[2 * t + 1];
+                            const float gx = fmaxf(0.0f, fmaxf(tl.x - qf[0], qf[0] - th.x));
+                            const float gy = fmaxf(0.0f, fmaxf(tl.y - qf[1], qf[1] - th.y));
+                            const float gz = fmaxf(0.0f, fmaxf(tl.z - qf[2], qf[2] - th.z));
+                            const float gap = sqrtf(gx * gx + gy * gy + gz * gz) * (1.0f - 8.0f * 5.9604645e-8f);
+                            reach = side == 0 ? !(th.w - gap < run - 2.0f * eps) : !(tl.w + gap > run + 2.0f * eps);
+                        }
+                        for (unsigned long long mk = __ballot(reach); mk; mk &= mk - 1)
+                            fn(c0 + __builtin_ctzll(mk));
+                    }
+                }
+            };
+            double best = side == 0 ? -INFINITY : INFINITY;
+            for_tiles([&](int t) {
+                for (int r = 0; r < TILE / 64; ++r) {
+                    const int64_t i = (int64_t)t * TILE + lane + 64 * r;
+                    if (i < n && near32(ps32[i], qf, side, run, eps)) {
+                        const double v = pair_val(samples + 4 * (int64_t)sperm[i], q, side);
+                        best = side == 0 ? fmax(best, v) : fmin(best, v);
+                    }
+                }
+            });
+            best = side == 0 ? wave_max(best) : wave_min(best);
+            if (lane == 0) rd[w] = best;
+            __syncthreads();
+            best = rd[0];
+            for (int j = 1; j < RL_W; ++j) best = side == 0 ? fmax(best, rd[j]) : fmin(best, rd[j]);
+            int64_t first = INT64_MAX;
+            int inband = 0;
+            for_tiles([&](int t) {
+                for (int r = 0; r < TILE / 64; ++r) {
+                    const int64_t i = (int64_t)t * TILE + lane + 64 * r;
+                    if (i < n && near32(ps32[i], qf, side, run, eps)) {
+                        const int64_t oi = sperm[i];
+                        const double v = pair_val(samples + 4 * oi, q, side);
+                        if (side == 0 ? (v >= best - tie) : (v <= best + tie)) {
+                            ++inband;
+                            first = oi < first ? oi : first;
+                        }
+                    }
+                }
+            });
+            first = wave_min_i64(first);
+            inband = wave_sum(inband);
+            if (lane == 0) {
+                ri[w] = first;
+                rc[w] = inband;
+            }
+            __syncthreads();
+            first = ri[0];
+            inband = rc[0];
+            for (int j = 1; j < RL_W; ++j) {
+                first = ri[j] < first ? ri[j] : first;
+                inband += rc[j];
+            }
+            __syncthreads();  // rd, ri, rc are reused
+            ext[side] = best;
+            arg[side] = first;
+            tied[side] = inband;
+            if (full && threadIdx.x == 0) atomicAdd((unsigned long long *)overflows, 1ull);
+        }
+        if (threadIdx.x == 0) {
+            const double s_a = arg[0] >= 0 && arg[0] < n ? samples[4 * arg[0] + 3] : 0.0;
+            const double s_b = arg[1] >= 0 && arg[1] < n ? samples[4 * arg[1] + 3] : 0.0;
+            write_query(qi, ext[0], ext[1], arg[0], arg[1], tied[0], tied[1], s_a, s_b, n, tol, tie, out);
+        }
+    }
 }
 
 // ---- float32 sweep over spatially sorted data ----
@@ -1178,7 +1207,7 @@ sdfi_status launch_sorted(const double *samples, int64_t n, const double *querie
     SDFI_HIP(hipGetLastError());
     // the queries whose candidate lists overflowed (usually none)
     KernelTimer t2("resolve", st);
-    resolve_list_kernel<<<RESOLVE_LIST_BLOCKS, 256, 0, st>>>(samples, n, queries, &sb.ext->eps, b.o, opt.tol,
+    resolve_list_kernel<<<RESOLVE_LIST_BLOCKS, RL_W * 64, 0, st>>>(samples, n, queries, &sb.ext->eps, b.o, opt.tol,
                                                              opt.tie_tol, out, b.overflows, sb.ovf_list,
                                                              reinterpret_cast<const unsigned long long *>(b.overflows + 2),
                                                              sb.sperm, sb.qperm, sb.ps, sb.tbox);
