@@ -194,7 +194,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 2), "peak": FP32_VECTOR_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK, 4), "traffic": recorded_traffic(),
                      "kernel": "sweep_sorted_kernel", "kernel_ms": round(sweep_ms, 3),
-                     "flop_per_launch": FLOP_PER_PAIR * evaluated},
+                     "flop_per_launch": FLOP_PER_PAIR * evaluated, "evaluated_pairs_per_launch": evaluated,
+                     "dense_pairs_per_launch": pairs},
     }
     if not args.no_greedy:
         c1 = configs.by_name("sphere16")

@@ -148,7 +148,8 @@ sdfi_status sdfi_timing_query(const char *name, double *ms, int64_t *launches);
  * a time, from the tile's box and value range, without evaluating them (their
  * values can neither be a bound nor lie within its tie band, so the results
  * equal those of the full sweep).  "bounds_list_overflows": query sides whose
- * candidate tile list overflowed, resolved by a scan of every tile.  Unknown
+ * candidate tile list overflowed, resolved by a scan of every tile that can
+ * reach the band.  Unknown
  * names give 0. */
 sdfi_status sdfi_counter_query(const char *name, int64_t *value);
 
