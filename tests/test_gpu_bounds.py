@@ -98,6 +98,26 @@ def test_bounds_balls64_sampled():
     assert np.all(lo[idx] <= phi + 1e-12) and np.all(phi <= hi[idx] + 1e-12)
 
 
+def test_culled_sweep_equals_dense_fp64():
+    # The float32 sweep rules out tiles and blocks from their box and value
+    # range; the float64 mode evaluates every pair.  Both resolve the final
+    # values with the same float64 pair arithmetic and tie rule, so on a
+    # workload where the culling is active the outputs are identical.
+    w = configs.ball_union(24, 1002)
+    print("culled vs dense: balls 24^3 x 48^3", flush=True)
+    s, q = dev(np.c_[w.points, w.values]), dev(w.queries)
+    sdfi.timing(True)
+    r32 = sdfi.bounds(s, q, "fp32")
+    torch.cuda.synchronize()
+    skipped = sdfi.counter_read("sweep_pairs_skipped")
+    sdfi.timing(False)
+    r64 = sdfi.bounds(s, q, "fp64")
+    torch.cuda.synchronize()
+    assert 0 < skipped < w.n * w.m
+    for x32, x64 in zip(r32, r64):
+        assert torch.equal(x32, x64)
+
+
 def test_bounds_empty_queries():
     out = sdfi.bounds(dev(np.array([[0.1, 0.2, 0.3, 0.1]])), torch.zeros((0, 3), dtype=torch.float64, device="cuda"))
     assert out[0].numel() == 0
