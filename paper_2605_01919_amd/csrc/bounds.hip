@@ -978,7 +978,7 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
             whi_all = wred_max(run_hi);
         }
     };
-    // Two passes over the tiles: the near ones first (direct formula), so that
+    // The near tiles first (direct formula), so that
     // the running extremes are already close to final when the far tiles are
     // swept on the matrix path and its group test can skip most square roots.
     // Tiles are classified 64 at a time, one per lane.
@@ -993,7 +993,10 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
     // reduces only the blocks of BLK samples that pass the same test at block
     // size (near tiles included, against the extremes as they stand: the
     // first near tiles are reduced whole).
-    for (int pass = 0; pass < 2; ++pass) {
+    // Pass 0 takes the near tiles overlapping the work-group's box, pass 1 the
+    // other near tiles (by then the block test prunes most of them), pass 2 the
+    // far tiles.
+    for (int pass = 0; pass < 3; ++pass) {
         for (int c0 = 0; c0 < ntiles; c0 += 64) {
             const int t = c0 + lane;
             bool in_pass = false, need = false;
@@ -1005,7 +1008,7 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
                 const float gz = fmaxf(0.0f, fmaxf(tl.z - qhi[2], qlo[2] - th.z));
                 const float gap = sqrtf(gx * gx + gy * gy + gz * gz);
                 const bool far = far_ok && cnt == TILE && gap > 0.0f && gap >= delta;
-                in_pass = far == (pass == 1);
+                in_pass = pass == 2 ? far : (!far && ((gap > 0.0f) == (pass == 1)));
                 need = in_pass;
                 if (in_pass && far) {
                     const float wx = fmaxf(0.0f, fmaxf(tl.x - wbox[w][3], wbox[w][0] - th.x));
@@ -1018,7 +1021,7 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
             const unsigned long long inpass = __ballot(in_pass);  // the same in every wavefront
             const unsigned long long mine = __ballot(need);
             unsigned long long todo = inpass;
-            if (pass == 1) {
+            if (pass == 2) {
                 nskipped += (unsigned long long)__popcll(inpass & ~mine) * TILE * vl;
                 if (lane == 0) wneed[phase][w] = mine;
                 __syncthreads();
@@ -1027,16 +1030,12 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
             }
             for (; todo; todo &= todo - 1) {
                 const int k = __builtin_ctzll(todo);
-                sweep_tile(c0 + k, pass == 1, ((mine >> k) & 1ull) != 0);
+                sweep_tile(c0 + k, pass == 2, ((mine >> k) & 1ull) != 0);
             }
-            if (pass == 1) {
+            if (pass == 2) {
                 wlo_all = wred_min(run_lo);
                 whi_all = wred_max(run_hi);
             }
-        }
-        if (pass == 0) {
-            wlo_all = wred_min(run_lo);
-            whi_all = wred_max(run_hi);
         }
     }
     // pairs ruled out without evaluation (stand-in lanes past m not counted)
