@@ -112,8 +112,8 @@ sdfi_status read_options(const sdfi_options *opt, sdfi_options *out) {
         set_error("grid must be in [0, 1024], got %d", out->grid);
         return SDFI_ERR_INVALID_ARGUMENT;
     }
-    if (out->block_size != 0 && out->block_size != 256 && out->block_size != 512 && out->block_size != 1024) {
-        set_error("block_size must be 0, 256, 512 or 1024, got %d", out->block_size);
+    if (out->block_size != 0 && out->block_size != 256 && out->block_size != 512) {
+        set_error("block_size must be 0, 256 or 512, got %d", out->block_size);
         return SDFI_ERR_INVALID_ARGUMENT;
     }
     for (int k = 0; k < 3; ++k) {

@@ -30,8 +30,9 @@ namespace sdfi {
 
 namespace {
 
-constexpr int NW = 8;  // wavefronts per greedy work-group
-constexpr int GBS = NW * 64;
+// Wavefronts per greedy work-group: 8 by default, 4 with block_size 256 (one
+// wavefront per SIMD, so the kernel may use twice the registers).
+constexpr int NW_DEFAULT = 8;
 
 enum {
     C_HI = 0, C_LO, C_ZERO, C_RMIN, C_COINC, C_INFEAS, C_UNRES, C_SEARCH, C_NUMERIC,
@@ -54,13 +55,14 @@ struct GInst {
     double *CW;              // (n + m) x 3 witnesses
     int64_t *CSRC;           // (n + m) query index of each appended constraint
     int64_t *list;           // 2 (n + m + 1) scratch
-    int32_t *flist;          // NW cap lists of fcap entries for the exhaustive searches
+    int32_t *flist;          // one cap list of fcap entries per wavefront, for the exhaustive searches
     int fcap;
     double *pend;            // (n + m) x 3 pending witness updates
     unsigned long long *counts;  // C_NCOUNT
     int64_t n, m;
 };
 
+template <int NW>
 struct StepShared {
     blk::Shared<NW> S;
     geom::Cap kp[NW][geom::KMAX];
@@ -78,8 +80,10 @@ __device__ inline bool in_domain(const double *w, const double *dlo, const doubl
 }
 
 // indices c with |W_c - q| < rn, in index order, into I.list; returns the count
+template <int NW>
 __device__ int64_t threatened(const GInst &I, int64_t N, const double *q, double rn, int64_t n, int64_t m,
-                              StepShared &SH) {
+                              StepShared<NW> &SH) {
+    constexpr int GBS = NW * 64;
     int64_t cnt = 0;
     if (rn > 0.0) {
         for (int64_t base = 0; base < N; base += GBS) {
@@ -120,8 +124,10 @@ __device__ inline void rim_hint(const double *o, double r, const double *q, doub
 // in parallel; results into I.pend.  SH.fail = 1 if some sphere has no
 // uncovered point left (with `keep_going` the search continues and such
 // spheres keep their old witness).
+template <int NW>
 __device__ void revalidate(const GInst &I, int64_t N, const double *q, double s, int64_t nthr, double tol,
-                           StepShared &SH, bool keep_going) {
+                           StepShared<NW> &SH, bool keep_going) {
+    constexpr int GBS = NW * 64;
     const int w = blk::wid(), ln = blk::lane();
     if (threadIdx.x == 0) {
         SH.fail = 0;
@@ -167,10 +173,12 @@ __device__ void revalidate(const GInst &I, int64_t N, const double *q, double s,
     __syncthreads();
 }
 
-__global__ __launch_bounds__(GBS) void greedy_kernel(const GInst *insts, double tol, double tie, double dlo0,
-                                                     double dlo1, double dlo2, double dhi0, double dhi1,
-                                                     double dhi2) {
-    __shared__ StepShared SH;
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void greedy_kernel(const GInst *insts, double tol, double tie, double dlo0,
+                                                         double dlo1, double dlo2, double dhi0, double dhi1,
+                                                         double dhi2) {
+    constexpr int GBS = NW * 64;
+    __shared__ StepShared<NW> SH;
     const GInst I = insts[blockIdx.x];
     const int tid = threadIdx.x;
     const int w = blk::wid(), ln = blk::lane();
@@ -464,7 +472,10 @@ struct GBufs {
     GInst *inst;
 };
 
-GBufs carve_greedy(Carver &c, int64_t n, int64_t m, int ninst) {
+// wavefronts per greedy work-group for these options
+int greedy_waves(const sdfi_options &o) { return o.block_size == 256 ? 4 : NW_DEFAULT; }
+
+GBufs carve_greedy(Carver &c, int64_t n, int64_t m, int ninst, int nw) {
     GBufs b;
     int64_t cap = n + m + 1;
     b.CP = c.take<double>(4 * cap);
@@ -473,7 +484,7 @@ GBufs carve_greedy(Carver &c, int64_t n, int64_t m, int ninst) {
     b.win = c.take<double>(3 * (n + 1));
     b.CSRC = c.take<int64_t>(cap);
     b.list = c.take<int64_t>(2 * (cap + ninst) + 2);
-    b.flist = c.take<int32_t>((int64_t)NW * (cap + ninst));
+    b.flist = c.take<int32_t>((int64_t)nw * (cap + ninst));
     b.wstat = c.take<uint8_t>(n + 1);
     b.counts = c.take<unsigned long long>(C_NCOUNT * ninst);
     b.order = c.take<int64_t>(m + 1);
@@ -498,7 +509,7 @@ sdfi_status run_witnesses(const double *samples, int64_t n, double *w, uint8_t *
 
 size_t greedy_ws(int64_t n, int64_t m, const sdfi_options &o) {
     Carver c(nullptr, 0, true);
-    carve_greedy(c, n, m, 1);
+    carve_greedy(c, n, m, 1, greedy_waves(o));
     Carver c2(nullptr, 0, true);
     size_t ord = order_ws(n, m, o);
     size_t cert = (o.flags & SDFI_OPT_CERTIFY) ? certify_ws(n + m, o) + 4 * (n + m) * 8 + 3 * (n + m) * 8 + 1024 : 0;
@@ -549,7 +560,8 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
                                  const sdfi_options &o, hipStream_t st) {
     const int64_t n = soff[ninst], m = qoff[ninst];
     Carver c(ws, ws_bytes);
-    GBufs b = carve_greedy(c, n + ninst, m, ninst);
+    const int nw = greedy_waves(o);
+    GBufs b = carve_greedy(c, n + ninst, m, ninst, nw);
     if (!c.ok()) {
         set_error("workspace too small for the greedy interpolation");
         return SDFI_ERR_WORKSPACE;
@@ -617,7 +629,7 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
         // each wave's cap list holds every ball of a small instance, FALLBACK_GLOBAL otherwise
         g.fcap = (int)std::min<int64_t>(geom::FALLBACK_GLOBAL, ni + mi + 1);
         g.flist = b.flist + fpos;
-        fpos += (int64_t)NW * g.fcap;
+        fpos += (int64_t)nw * g.fcap;
         g.counts = b.counts + C_NCOUNT * i;
         g.n = ni;
         g.m = mi;
@@ -625,8 +637,13 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
     }
     SDFI_HIP(hipMemcpyAsync(b.inst, hi.data(), sizeof(GInst) * ninst, hipMemcpyHostToDevice, st));
     KernelTimer tm("greedy", st);
-    greedy_kernel<<<ninst, GBS, 0, st>>>(b.inst, o.tol, o.tie_tol, o.domain_lo[0], o.domain_lo[1], o.domain_lo[2],
-                                         o.domain_hi[0], o.domain_hi[1], o.domain_hi[2]);
+    if (nw == 4)
+        greedy_kernel<4><<<ninst, 4 * 64, 0, st>>>(b.inst, o.tol, o.tie_tol, o.domain_lo[0], o.domain_lo[1],
+                                                   o.domain_lo[2], o.domain_hi[0], o.domain_hi[1], o.domain_hi[2]);
+    else
+        greedy_kernel<NW_DEFAULT><<<ninst, NW_DEFAULT * 64, 0, st>>>(b.inst, o.tol, o.tie_tol, o.domain_lo[0],
+                                                                     o.domain_lo[1], o.domain_lo[2], o.domain_hi[0],
+                                                                     o.domain_hi[1], o.domain_hi[2]);
     tm.stop();
     SDFI_HIP(hipGetLastError());
     std::vector<unsigned long long> cnt(C_NCOUNT * ninst);

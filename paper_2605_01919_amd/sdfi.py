@@ -209,13 +209,14 @@ def sample_witnesses(samples):
     return w, st
 
 
-def greedy(samples, queries, order=None, grid=0, certify=False, input_check=False, sample_witness=False):
+def greedy(samples, queries, order=None, grid=0, certify=False, input_check=False, sample_witness=False,
+           block_size=0):
     """Greedy interpolation.  Returns a dict of GPU tensors and the host report."""
     samples = _dev(samples, torch.float64, 4, "samples")
     queries = _dev(queries, torch.float64, 3, "queries")
     n, m = samples.shape[0], queries.shape[0]
     flags = (OPT_CERTIFY if certify else 0) | (OPT_INPUT_CHECK if input_check else 0)
-    opt = options(grid=grid, flags=flags)
+    opt = options(grid=grid, flags=flags, block_size=block_size)
     dev = samples.device
     if order is not None:
         order = _dev(order, torch.int64, None, "order")
@@ -238,7 +239,7 @@ def greedy(samples, queries, order=None, grid=0, certify=False, input_check=Fals
     return out
 
 
-def greedy_batched(instances, certify=False):
+def greedy_batched(instances, certify=False, block_size=0):
     """instances: list of (samples (n_i,4), queries (8 n_i,3), grid_i) GPU tensors."""
     soff = [0]
     qoff = [0]
@@ -251,7 +252,7 @@ def greedy_batched(instances, certify=False):
     so = (ctypes.c_int64 * len(soff))(*soff)
     qo = (ctypes.c_int64 * len(qoff))(*qoff)
     n, m = soff[-1], qoff[-1]
-    opt = options(flags=OPT_CERTIFY if certify else 0)
+    opt = options(flags=OPT_CERTIFY if certify else 0, block_size=block_size)
     dev = samples.device
     out = {
         "values": torch.empty(m, dtype=torch.float64, device=dev),

@@ -113,6 +113,20 @@ def test_greedy_runs_twice_identically():
     assert torch.equal(a["active"], b["active"])
 
 
+def test_greedy_block_size_gives_identical_results():
+    # 4 or 8 wavefronts per instance: the decisions are exact answers and the
+    # reductions order-independent, so values, kinds and parents agree
+    w = configs.ball_union(6)
+    print("greedy balls6 with 256 and 512 threads", flush=True)
+    s, q = dev(np.c_[w.points, w.values]), dev(w.queries)
+    a = sdfi.greedy(s, q, grid=w.grid, block_size=256, certify=True)
+    b = sdfi.greedy(s, q, grid=w.grid, block_size=512, certify=True)
+    assert torch.equal(a["values"], b["values"]) and torch.equal(a["kind"], b["kind"])
+    assert torch.equal(a["active"], b["active"])
+    for r in (a["report"], b["report"]):
+        assert r["n_violations_pairwise"] == 0 and r["n_violations_witness"] == 0
+
+
 def test_input_check_rejects_covered_sample():
     P = np.array([[0.2, 0.2, 0.2], [0.22, 0.2, 0.2], [0.6, 0.6, 0.6]])
     S = np.array([0.15, 0.05, 0.1])
