@@ -53,13 +53,6 @@ struct Pt4 {
     T x, y, z, s;
 };
 
-__global__ void pack_f32_kernel(const double *__restrict__ samples, float4 *__restrict__ out, int64_t n) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) {
-        const double *p = samples + 4 * i;
-        out[i] = make_float4((float)p[0], (float)p[1], (float)p[2], (float)p[3]);
-    }
-}
 
 __device__ inline float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ inline double fsqrt(double x) { return sqrt(x); }
@@ -1120,14 +1113,12 @@ SortedBufs carve_sorted(Carver &c, int64_t n, int64_t m) {
 template <typename T>
 struct SweepBufs {
     SweepOut<T> o;
-    Pt4<T> *pts;
     int64_t *overflows;  // [0] list overflows, [1] pairs the sorted sweep skipped, [2] its overflowed slots
 };
 
 template <typename T>
 SweepBufs<T> carve_sweep(Carver &c, int64_t n, int64_t m) {
     SweepBufs<T> b;
-    b.pts = std::is_same<T, float>::value ? c.take<Pt4<T>>(n) : nullptr;
     b.o.run = c.take<T>(2 * m);
     b.o.count = c.take<uint32_t>(2 * m);
     b.o.tiles = c.take<int32_t>(2 * m * LIST);
@@ -1145,13 +1136,8 @@ sdfi_status launch(const double *samples, int64_t n, const double *queries, int6
         set_error("workspace too small for the bound sweep");
         return SDFI_ERR_WORKSPACE;
     }
-    const Pt4<T> *pts;
-    if (std::is_same<T, float>::value) {
-        pack_f32_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(samples, (float4 *)b.pts, n);
-        pts = b.pts;
-    } else {
-        pts = reinterpret_cast<const Pt4<T> *>(samples);
-    }
+    static_assert(std::is_same<T, double>::value, "the unsorted sweep serves the float64 mode");
+    const Pt4<T> *pts = reinterpret_cast<const Pt4<T> *>(samples);
     SDFI_HIP(hipMemsetAsync(b.overflows, 0, 3 * sizeof(int64_t), st));
     const int64_t per = (int64_t)BT * QPT;
     KernelTimer t1("sweep", st);
@@ -1221,11 +1207,6 @@ sdfi_status launch_sorted(const double *samples, int64_t n, const double *querie
 
 }  // namespace
 
-// float32 pair value error: inputs rounded (<= 2^-24 relative each), three
-// subtractions, the squared sum and v_sqrt_f32 (1 ulp): well under 5e-7 for
-// coordinates and values of magnitude <= 2; two values may err in opposite
-// directions, hence 2 x 5e-7 plus the tie band.
-static double eps_f32(const sdfi_options &o) { return 2.0 * 5e-7 + o.tie_tol + 1e-6; }
 static double eps_f64(const sdfi_options &o) { return o.tie_tol * 1.001 + 1e-15; }
 
 size_t bounds_ws(int64_t n, int64_t m, const sdfi_options &o) {
