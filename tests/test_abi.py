@@ -65,3 +65,24 @@ def test_workspace_sizes_grow():
         assert L.sdfi_workspace_size(op, 100, 100, ctypes.byref(o), ctypes.byref(s1)) == 0
         assert L.sdfi_workspace_size(op, 10000, 10000, ctypes.byref(o), ctypes.byref(s2)) == 0
         assert s2.value >= s1.value > 0
+
+
+def test_counters_and_block_size_on_host():
+    L = sdfi.lib()
+    v = ctypes.c_int64(-1)
+    L.sdfi_timing_reset()
+    assert L.sdfi_counter_query(b"sweep_pairs_skipped", ctypes.byref(v)) == 0 and v.value == 0
+    assert L.sdfi_counter_query(b"no_such_counter", ctypes.byref(v)) == 0 and v.value == 0
+    assert L.sdfi_counter_query(None, ctypes.byref(v)) == 1
+    # 256 or 512 threads per greedy work-group (0 = 512); 4 wavefronts need
+    # half the per-wavefront cap lists
+    size = ctypes.c_size_t()
+    sizes = {}
+    for bs in (0, 256, 512):
+        o = sdfi.options(block_size=bs)
+        assert L.sdfi_workspace_size(4, 5000, 40000, ctypes.byref(o), ctypes.byref(size)) == 0
+        sizes[bs] = size.value
+    assert sizes[0] == sizes[512] > sizes[256]
+    o = sdfi.options(block_size=1024)
+    assert L.sdfi_workspace_size(4, 5000, 40000, ctypes.byref(o), ctypes.byref(size)) == 1
+    assert b"block_size" in L.sdfi_last_error()
