@@ -118,6 +118,24 @@ def test_culled_sweep_equals_dense_fp64():
         assert torch.equal(x32, x64)
 
 
+def test_bounds_unpacked_lists_over_2_24_samples():
+    # More than 65536 tiles of 256 samples (257^3): the candidate lists hold
+    # plain tile indices and the resolve tests every block of a listed tile
+    # by its box; the results still equal the dense float64 sweep's.
+    g = 257
+    p = configs.grid_centres(g)
+    v = np.linalg.norm(p - 0.5, axis=1) - 0.3  # exact SDF of a sphere
+    q = np.random.default_rng(2003).uniform(0.0, 1.0, size=(4096, 3))
+    print("bounds with 257^3 samples x 4096 queries", flush=True)
+    s, qq = dev(np.c_[p, v]), dev(q)
+    del p, v
+    r32 = sdfi.bounds(s, qq, "fp32")
+    r64 = sdfi.bounds(s, qq, "fp64")
+    torch.cuda.synchronize()
+    for x32, x64 in zip(r32, r64):
+        assert torch.equal(x32, x64)
+
+
 def test_bounds_empty_queries():
     out = sdfi.bounds(dev(np.array([[0.1, 0.2, 0.3, 0.1]])), torch.zeros((0, 3), dtype=torch.float64, device="cuda"))
     assert out[0].numel() == 0
