@@ -17,5 +17,6 @@ Modules (each function cites the passage it follows):
   certify  Prop. 1 certificate of a final sample set
   repair   pseudo-SDF repair (Sec. 6)
   adjoint  reverse sweep of d(sum of values)/d(inputs) over active parents
-  tiny     paper-exact candidate scoring for tiny inputs (Def. 1, Sec. 3.3)
+  tiny     paper-exact tier for tiny inputs: every Def. 1 grow-to point, the
+           Sec. 3.3 scoring rule and Prop. 1 checked on the whole set
 """

@@ -22,12 +22,15 @@ import numpy as np
 from .common import (KIND_COINCIDENT, KIND_HI, KIND_LO, KIND_RMIN_T, dist, sign_class)
 
 
-def adjoint(P, S, Q, values, kind, active, order):
+def adjoint(P, S, Q, values, kind, active, order, grad_values=None):
+    """Gradient of sum_j grad_values[j] * values[j] (all weights 1 by default)
+    with respect to the sample values and positions, decisions held fixed.
+    Returns (grad_s, grad_p, number of multi-parent values met)."""
     P = np.asarray(P, dtype=np.float64)
     S = np.asarray(S, dtype=np.float64)
     Q = np.asarray(Q, dtype=np.float64)
     n = len(S)
-    g = np.ones(len(Q))
+    g = np.ones(len(Q)) if grad_values is None else np.array(grad_values, dtype=np.float64)
     grad_s = np.zeros(n)
     grad_p = np.zeros((n, 3))
     multi = 0
