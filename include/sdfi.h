@@ -174,6 +174,26 @@ sdfi_status sdfi_bounds(const double *samples, int64_t n, const double *queries,
                         double *lo, double *hi, int32_t *argmax, int32_t *argmin, uint32_t *flags,
                         void *ws, size_t ws_bytes, const sdfi_options *opt, sdfi_stream stream);
 
+/* sdfi_bounds for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * kernels and results, with the workspace taken from a scratch array of
+ * 64 MiB that the library holds in device memory (one per GPU, kept until the
+ * process ends) instead of a caller workspace.  Nothing is allocated: no
+ * hipMalloc, no events, no pinned memory (kernel timers and work counters
+ * record nothing during this call).  The caller still provides inputs and
+ * outputs as for sdfi_bounds.
+ * Limit: sizes whose sdfi_workspace_size(SDFI_OP_BOUNDS, n, m, opt) exceeds
+ * 64 MiB are rejected with SDFI_ERR_UNSUPPORTED before any device work (e.g.
+ * n = 110592, m = 262144 fits in either precision).
+ * Every call on one GPU uses that GPU's one array: calls that overlap on the
+ * same GPU (different streams or threads without ordering) race and give
+ * wrong results; calls ordered on one stream are safe.  The first call on a
+ * device looks the array's address up (hipGetSymbolAddress) with that device
+ * current.  Asynchronous. */
+sdfi_status sdfi_bounds_noalloc(const double *samples, int64_t n, const double *queries, int64_t m, double *lo,
+                                double *hi, int32_t *argmax, int32_t *argmin, uint32_t *flags,
+                                const sdfi_options *opt, sdfi_stream stream);
+
 /* Certificate of Prop. 1 for a final set of N samples (pts_values N x 4)
  * with one claimed uncovered point per sphere (witness N x 3):
  *   (i)  |s_x - s_y| <= |p_x - p_y| + tol for every pair;

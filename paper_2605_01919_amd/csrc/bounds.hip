@@ -36,6 +36,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <cfloat>
+#include <mutex>
 #include <cmath>
 
 namespace sdfi {
@@ -1070,6 +1071,12 @@ __global__ __launch_bounds__(MQ) void sweep_sorted_kernel(const float4 *__restri
     }
 }
 
+// the sweeps' counters start at zero (a kernel rather than a memset node, so a
+// caller may capture the launches in a graph)
+__global__ void zero_i64_kernel(int64_t *p, int k) {
+    if ((int)threadIdx.x < k) p[threadIdx.x] = 0;
+}
+
 // workspace of the sorted float32 path
 struct SortedBufs {
     ExtPart *parts;
@@ -1138,7 +1145,7 @@ sdfi_status launch(const double *samples, int64_t n, const double *queries, int6
     }
     static_assert(std::is_same<T, double>::value, "the unsorted sweep serves the float64 mode");
     const Pt4<T> *pts = reinterpret_cast<const Pt4<T> *>(samples);
-    SDFI_HIP(hipMemsetAsync(b.overflows, 0, 3 * sizeof(int64_t), st));
+    zero_i64_kernel<<<1, 64, 0, st>>>(b.overflows, 3);
     const int64_t per = (int64_t)BT * QPT;
     KernelTimer t1("sweep", st);
     sweep_kernel<T, QPT><<<(unsigned)((m + per - 1) / per), BT, 0, st>>>(pts, (int)n, queries, m, eps, b.o);
@@ -1178,7 +1185,7 @@ sdfi_status launch_sorted(const double *samples, int64_t n, const double *querie
     SDFI_HIP(hipcub::DeviceRadixSort::SortPairs(sb.cub, sb.cub_bytes, sb.keys_in, sb.keys_out, sb.idx_in, sb.qperm,
                                                 (int)m, 0, 30, st));
     SDFI_HIP(hipGetLastError());
-    SDFI_HIP(hipMemsetAsync(b.overflows, 0, 3 * sizeof(int64_t), st));
+    zero_i64_kernel<<<1, 64, 0, st>>>(b.overflows, 3);
     const BoundsOut out{lo, hi, argmax, argmin, flags};
     const Fused fused{sb.ps64, sb.sperm, opt.tol, opt.tie_tol, out, sb.ovf_list,
                       reinterpret_cast<unsigned long long *>(b.overflows + 2)};
@@ -1249,5 +1256,73 @@ extern "C" sdfi_status sdfi_bounds(const double *samples, int64_t n, const doubl
         return SDFI_ERR_WORKSPACE;
     }
     Carver c(ws, ws_bytes);
+    return run_bounds(samples, n, queries, m, lo, hi, argmax, argmin, flags, c, o, to_hip(stream), nullptr);
+}
+
+// ---- the bound sweep without allocation ----
+//
+// A file-scope device array serves as the workspace of sdfi_bounds_noalloc.
+// Host code never passes the array's name to a kernel or a copy (on the host
+// it is a stand-in, not a device address): the device address is looked up
+// once per device with hipGetSymbolAddress, with that device current, and
+// kept in g_scratch_ptr.
+namespace sdfi {
+namespace {
+
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+constexpr int MAX_DEVICES = 64;
+
+__device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+sdfi_status scratch_of_current_device(void **out) {
+    int dev = 0;
+    SDFI_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        set_error("device ordinal %d beyond the %d supported by the allocation-free entry point", dev, MAX_DEVICES);
+        return SDFI_ERR_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        SDFI_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) {
+            set_error("hipGetSymbolAddress returned a null address for the scratch array");
+            return SDFI_ERR_DEVICE;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SDFI_OK;
+}
+
+}  // namespace
+}  // namespace sdfi
+
+extern "C" sdfi_status sdfi_bounds_noalloc(const double *samples, int64_t n, const double *queries, int64_t m,
+                                           double *lo, double *hi, int32_t *argmax, int32_t *argmin,
+                                           uint32_t *flags, const sdfi_options *opt, sdfi_stream stream) {
+    using namespace sdfi;
+    NoAllocScope no_alloc;
+    sdfi_options o;
+    sdfi_status s = read_options(opt, &o);
+    if (s != SDFI_OK) return s;
+    SDFI_CHECK_ARG(n >= 1 && n < (int64_t(1) << 31), "n must be in [1, 2^31), got %lld", (long long)n);
+    SDFI_CHECK_ARG(m >= 0 && m < (int64_t(1) << 31), "m must be in [0, 2^31), got %lld", (long long)m);
+    if (m == 0) return SDFI_OK;
+    SDFI_CHECK_ARG(samples && queries && lo && hi && argmax && argmin && flags, "null array argument");
+    const size_t need = bounds_ws(n, m, o);
+    if (need > NOALLOC_SCRATCH_BYTES) {
+        set_error("n = %lld, m = %lld need %zu bytes of scratch, beyond the %zu of the allocation-free entry point "
+                  "(use sdfi_bounds with a workspace)",
+                  (long long)n, (long long)m, need, NOALLOC_SCRATCH_BYTES);
+        return SDFI_ERR_UNSUPPORTED;
+    }
+    void *ws = nullptr;
+    s = scratch_of_current_device(&ws);
+    if (s != SDFI_OK) return s;
+    Carver c(ws, NOALLOC_SCRATCH_BYTES);
     return run_bounds(samples, n, queries, m, lo, hi, argmax, argmin, flags, c, o, to_hip(stream), nullptr);
 }

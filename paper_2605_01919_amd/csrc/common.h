@@ -32,6 +32,15 @@ void set_error(const char *fmt, ...);
         }                                                                       \
     } while (0)
 
+// While an entry point that must not allocate runs on this thread, timers and
+// work counters record nothing (they create events and pinned host words).
+extern thread_local bool g_no_alloc;
+struct NoAllocScope {
+    bool prev;
+    NoAllocScope() : prev(g_no_alloc) { g_no_alloc = true; }
+    ~NoAllocScope() { g_no_alloc = prev; }
+};
+
 // Records a pair of HIP events around a kernel when timing is enabled.
 struct KernelTimer {
     hipEvent_t a = nullptr, b = nullptr;

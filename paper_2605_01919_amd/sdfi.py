@@ -73,7 +73,7 @@ def lib():
 
 
 EXPORTS = ["sdfi_default_options", "sdfi_last_error", "sdfi_version", "sdfi_timing_enable", "sdfi_timing_query",
-           "sdfi_counter_query", "sdfi_timing_reset", "sdfi_workspace_size", "sdfi_bounds",
+           "sdfi_counter_query", "sdfi_timing_reset", "sdfi_workspace_size", "sdfi_bounds", "sdfi_bounds_noalloc",
            "sdfi_certify", "sdfi_refinement_order", "sdfi_sample_witnesses", "sdfi_greedy_interpolate",
            "sdfi_greedy_interpolate_batched", "sdfi_min_valid_radius", "sdfi_repair", "sdfi_greedy_backward"]
 
@@ -164,6 +164,25 @@ def bounds(samples, queries, precision="fp32"):
     _check(lib().sdfi_bounds(_ptr(samples), ctypes.c_int64(n), _ptr(queries), ctypes.c_int64(m), _ptr(lo),
                              _ptr(hi), _ptr(a), _ptr(b), _ptr(f), _ptr(ws), ctypes.c_size_t(ws.numel()),
                              ctypes.byref(opt), _stream()), "sdfi_bounds")
+    return lo, hi, a, b, f
+
+
+def bounds_noalloc(samples, queries, precision="fp32"):
+    """sdfi_bounds through the entry point that allocates nothing (its
+    workspace is the library's scratch array; sizes are limited)."""
+    samples = _dev(samples, torch.float64, 4, "samples")
+    queries = _dev(queries, torch.float64, 3, "queries")
+    n, m = samples.shape[0], queries.shape[0]
+    opt = options(precision)
+    dev = samples.device
+    lo = torch.empty(m, dtype=torch.float64, device=dev)
+    hi = torch.empty(m, dtype=torch.float64, device=dev)
+    a = torch.empty(m, dtype=torch.int32, device=dev)
+    b = torch.empty(m, dtype=torch.int32, device=dev)
+    f = torch.empty(m, dtype=torch.int32, device=dev)
+    _check(lib().sdfi_bounds_noalloc(_ptr(samples), ctypes.c_int64(n), _ptr(queries), ctypes.c_int64(m), _ptr(lo),
+                                     _ptr(hi), _ptr(a), _ptr(b), _ptr(f), ctypes.byref(opt), _stream()),
+           "sdfi_bounds_noalloc")
     return lo, hi, a, b, f
 
 

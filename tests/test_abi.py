@@ -86,3 +86,17 @@ def test_counters_and_block_size_on_host():
     o = sdfi.options(block_size=1024)
     assert L.sdfi_workspace_size(4, 5000, 40000, ctypes.byref(o), ctypes.byref(size)) == 1
     assert b"block_size" in L.sdfi_last_error()
+
+
+def test_noalloc_rejects_sizes_beyond_its_scratch():
+    # rejected on the host before any device work (the dummy addresses are
+    # never touched)
+    L = sdfi.lib()
+    o = sdfi.options()
+    fake = [ctypes.c_void_p(256 * (k + 1)) for k in range(7)]
+    st = L.sdfi_bounds_noalloc(fake[0], ctypes.c_int64(262144), fake[1], ctypes.c_int64(2097152), *fake[2:],
+                               ctypes.byref(o), None)
+    assert st == 6 and b"scratch" in L.sdfi_last_error()
+    st = L.sdfi_bounds_noalloc(None, ctypes.c_int64(10), None, ctypes.c_int64(5), None, None, None, None, None,
+                               ctypes.byref(o), None)
+    assert st == 1
