@@ -44,7 +44,7 @@ typedef enum {
     SDFI_ERR_DEVICE = 2,           /* a HIP call failed */
     SDFI_ERR_WORKSPACE = 3,        /* ws_bytes below sdfi_workspace_size() */
     SDFI_ERR_INVALID_INPUT = 4,    /* input samples violate Prop. 1 (when checked) */
-    SDFI_ERR_DOMAIN = 5,           /* a point outside the domain box */
+    SDFI_ERR_DOMAIN = 5,           /* a point outside the domain box, or off the stated grid */
     SDFI_ERR_UNSUPPORTED = 6,      /* size beyond a documented limit */
     SDFI_ERR_NUMERIC = 7           /* an internal search hit its iteration cap */
 } sdfi_status;
@@ -83,7 +83,7 @@ enum {
 /* option flags */
 enum {
     SDFI_OPT_CERTIFY = 1,      /* greedy/repair: run the Prop. 1 certificate on the result */
-    SDFI_OPT_INPUT_CHECK = 2   /* greedy: fail with SDFI_ERR_INVALID_INPUT if an input sphere is fully covered */
+    SDFI_OPT_INPUT_CHECK = 2   /* greedy: fail with SDFI_ERR_INVALID_INPUT if the samples violate Prop. 1 */
 };
 
 typedef struct {
@@ -169,7 +169,10 @@ sdfi_status sdfi_workspace_size(sdfi_op op, int64_t n, int64_t m, const sdfi_opt
  *   argmax[j] / argmin[j] = smallest i within tie_tol of lo / hi
  *   flags[j] = SDFI_FLAG_* bits.
  * samples n x 4, queries m x 3; outputs have m entries (argmax/argmin int32).
- * n >= 1; m >= 0 (m = 0 is a no-op).  n < 2^31.  Asynchronous. */
+ * n >= 1; m >= 0 (m = 0 is a no-op).  n < 2^31.  Asynchronous: the inputs
+ * are not checked on the host, so a sample with a NaN coordinate or value
+ * takes part in no extreme, and a query with a NaN coordinate gets
+ * lo = -inf, hi = +inf and argmax = argmin = -1. */
 sdfi_status sdfi_bounds(const double *samples, int64_t n, const double *queries, int64_t m,
                         double *lo, double *hi, int32_t *argmax, int32_t *argmin, uint32_t *flags,
                         void *ws, size_t ws_bytes, const sdfi_options *opt, sdfi_stream stream);
@@ -200,7 +203,9 @@ sdfi_status sdfi_bounds_noalloc(const double *samples, int64_t n, const double *
  *   (ii) every witness lies on its sphere (within tol) and in no other
  *        open ball (|w - p_y| >= |s_y| - tol, with 1e-9 rounding slack).
  * Rows whose value is NaN (queries left without a value) are not part of
- * the set.  Counts go to report->n_violations_pairwise / _witness and
+ * the set.  The float32 screen's band is derived on the device from the
+ * largest coordinate and value magnitudes, so the counts equal a float64
+ * evaluation at any scale.  Counts go to report->n_violations_pairwise / _witness and
  * report->pairs_evaluated.  `report` is host memory and required;
  * synchronises the stream. */
 sdfi_status sdfi_certify(const double *pts_values, const double *witness, int64_t N, sdfi_report *report,
@@ -216,7 +221,9 @@ sdfi_status sdfi_certify(const double *pts_values, const double *witness, int64_
  * Otherwise the m scattered queries are bucketed by the input cell holding
  * them (cells in flood-fill order, queries of one cell by index).
  * order_out: m int64 (device).  Synchronises the stream (the flood fill
- * runs on the host). */
+ * runs on the host).  SDFI_ERR_DOMAIN if sample i does not lie in cell i of
+ * that grid (x fastest); SDFI_ERR_INVALID_ARGUMENT for NaN or infinite
+ * inputs. */
 sdfi_status sdfi_refinement_order(const double *samples, int64_t n, const double *queries, int64_t m,
                                   int64_t *order_out, void *ws, size_t ws_bytes, const sdfi_options *opt,
                                   sdfi_stream stream);
@@ -241,6 +248,16 @@ sdfi_status sdfi_sample_witnesses(const double *samples, int64_t n, double *witn
  *   kind: m uint8 (SDFI_KIND_*); witness: m x 3 (an uncovered point of each
  *   query sphere, as last updated); sample_witness: n x 3 or NULL.
  * m < 2^31 and n + m < 2^31.  Synchronises the stream.
+ * Errors (found before the greedy starts): SDFI_ERR_INVALID_ARGUMENT for NaN
+ * or infinite inputs or an order_in that is not a permutation of [0, m);
+ * SDFI_ERR_DOMAIN for a sample or query point outside the domain box,
+ * or (order_in NULL) sample i or query j outside cell i (j) of the N^3
+ * ((2N)^3) grid; with SDFI_OPT_INPUT_CHECK, SDFI_ERR_INVALID_INPUT
+ * when the samples violate Prop. 1 (a sphere without an uncovered point, or
+ * a pair breaking the cone: opposite-sign spheres that intersect, or a
+ * sphere inside another's ball).  Without INPUT_CHECK such inputs are
+ * interpolated as given: a query whose bounds contradict (lo > hi + tol)
+ * gets kind SDFI_KIND_INFEASIBLE and value NaN.
  * report (host, may be NULL): counts; ms_phase[0] order, [1] witnesses,
  * [2] greedy, [3] certificate; [4..7] device time of the greedy steps spent
  * in the bound scans, the candidate checks, the minimum valid radius and the
@@ -271,7 +288,9 @@ sdfi_status sdfi_greedy_interpolate_batched(int32_t num_instances, const int64_t
  * with the sign forced by containment (0 and SDFI_KIND_ZERO outside every
  * ball).  By Corollary 1 all outputs are jointly valid with the samples.
  * values m float64, kind m uint8, witness m x 3 (the contact point).
- * Asynchronous. */
+ * Synchronises the stream (input check): SDFI_ERR_INVALID_ARGUMENT for NaN
+ * or infinite inputs, SDFI_ERR_DOMAIN for a sample or query point outside
+ * the domain box. */
 sdfi_status sdfi_min_valid_radius(const double *samples, int64_t n, const double *queries, int64_t m,
                                   double *values, uint8_t *kind, double *witness, void *ws, size_t ws_bytes,
                                   const sdfi_options *opt, sdfi_stream stream);
@@ -283,7 +302,9 @@ sdfi_status sdfi_min_valid_radius(const double *samples, int64_t n, const double
  *   repaired: n (kept samples unchanged); removed: n uint8;
  *   query_values: m; kind: n + m uint8 (KEPT, RMIN_*, ZERO, UNRESOLVED).
  * Synchronises the stream.  report (may be NULL): n_removed, ms_phase[0]
- * detection, [1] removal, [2] radii. */
+ * detection, [1] removal, [2] radii.  SDFI_ERR_INVALID_ARGUMENT for NaN or
+ * infinite inputs, SDFI_ERR_DOMAIN for a sample or query point outside the
+ * domain box. */
 sdfi_status sdfi_repair(const double *samples, int64_t n, const double *queries, int64_t m, double *repaired,
                         uint8_t *removed, double *query_values, uint8_t *kind, sdfi_report *report, void *ws,
                         size_t ws_bytes, const sdfi_options *opt, sdfi_stream stream);

@@ -26,7 +26,8 @@ def certify(P, S, W, tol=TOL, chunk=1024):
     sig = sign_class(S)
     R = np.abs(S)
     out = {"pair_opposite": 0, "pair_same": 0, "witness_off_sphere": 0, "witness_covered": 0,
-           "witness_missing": int(np.isnan(W).any(1).sum()), "pairs_checked": 0}
+           "witness_missing": int(np.isnan(W).any(1).sum()), "pairs_checked": 0,
+           "spheres_without_witness": 0}
     for s0 in range(0, N, chunk):
         rows = slice(s0, min(N, s0 + chunk))
         d = dist(P[rows, None, :], P[None, :, :])
@@ -46,6 +47,8 @@ def certify(P, S, W, tol=TOL, chunk=1024):
         out["witness_covered"] += int(cov.any(1).sum())
         off = np.abs(dist(W[rows], P[rows]) - R[rows]) > tol
         out["witness_off_sphere"] += int(off.sum())
+        # spheres whose witness fails either way (or is missing), each once
+        out["spheres_without_witness"] += int((cov.any(1) | ~(np.abs(dist(W[rows], P[rows]) - R[rows]) <= tol)).sum())
     out["violations"] = (out["pair_opposite"] + out["pair_same"] + out["witness_off_sphere"]
                          + out["witness_covered"] + out["witness_missing"])
     return out

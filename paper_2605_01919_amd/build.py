@@ -1,6 +1,7 @@
 """Builds libsdfi.so (all HIP sources, gfx950) next to this file."""
 from __future__ import annotations
 
+import concurrent.futures
 import glob
 import os
 import subprocess
@@ -24,15 +25,21 @@ def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
+def _compile(src, verbose):
+    obj = os.path.join(HERE, "csrc", os.path.basename(src) + ".o")
+    cmd = ["hipcc", "-c", *[f for f in FLAGS if f != "-shared"], src, "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    return obj
+
+
 def build(verbose: bool = False) -> str:
-    objs = []
-    for src in sources():
-        obj = os.path.join(HERE, "csrc", os.path.basename(src) + ".o")
-        cmd = ["hipcc", "-c", *[f for f in FLAGS if f != "-shared"], src, "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
-        objs.append(obj)
+    # one hipcc per source, several at a time (each is single-threaded)
+    srcs = sources()
+    workers = max(1, min(len(srcs), (os.cpu_count() or 1), 8))
+    with concurrent.futures.ThreadPoolExecutor(workers) as pool:
+        objs = list(pool.map(lambda s: _compile(s, verbose), srcs))
     tmp = LIB + ".tmp"
     subprocess.check_call(["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp])
     os.replace(tmp, LIB)

@@ -1,10 +1,16 @@
 // Certificate of Prop. 1 over a final sample set (pairwise cone + witnesses).
 //
 // Every pair is screened in float32; pairs whose float32 margin is within
-// eps of the threshold (eps above the float32 error of a margin) are decided
-// in float64, so the counts equal a pure float64 evaluation.  Rows whose
-// value is NaN (queries the greedy left without a value) are not part of the
-// set: every comparison with them is false and their witness is not checked.
+// eps of the threshold are decided in float64, so the counts equal a pure
+// float64 evaluation.  eps comes from the data on the device: with u the
+// float32 unit roundoff, Mc the largest |coordinate| (points and witnesses)
+// and Ms the largest |value|, a float32 distance errs by at most 28 u Mc
+// (inputs rounded: 2 sqrt3 u Mc; differences: sqrt3 u Mc; squares, sum and
+// sqrt: 6 u d with d <= 2 sqrt3 Mc), a difference of two values by 4 u Ms
+// and the final subtraction by u (2 sqrt3 Mc + 2 Ms), so a margin errs by
+// less than u (32 Mc + 6 Ms); eps is twice that.  Rows whose value is NaN
+// (queries the greedy left without a value) are not part of the set: every
+// comparison with them is false and their witness is not checked.
 #include "common.h"
 
 #include <cmath>
@@ -22,6 +28,38 @@ struct Cnt {
     unsigned long long wit;
 };
 
+// largest finite |coordinate| of points and witnesses and largest finite |value|
+// (as float bits: non-negative floats order like their bit patterns); the
+// counters start at zero here (a kernel, not a memset)
+__global__ void mag_init_kernel(unsigned *mag, Cnt *cnt) {
+    if (threadIdx.x == 0) {
+        mag[0] = mag[1] = 0u;
+        cnt->pair = cnt->wit = 0ull;
+    }
+}
+
+__global__ void mag_kernel(const double *__restrict__ pv, const double *__restrict__ wit, int64_t N, unsigned *mag) {
+    float mc = 0.0f, ms = 0.0f;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += stride) {
+        for (int k = 0; k < 3; ++k) {
+            const double x = fabs(pv[4 * i + k]), w = fabs(wit[3 * i + k]);
+            if (isfinite(x)) mc = fmaxf(mc, (float)x);
+            if (isfinite(w)) mc = fmaxf(mc, (float)w);
+        }
+        const double v = fabs(pv[4 * i + 3]);
+        if (isfinite(v)) ms = fmaxf(ms, (float)v);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        mc = fmaxf(mc, __shfl_xor(mc, o, 64));
+        ms = fmaxf(ms, __shfl_xor(ms, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&mag[0], __float_as_uint(mc));
+        atomicMax(&mag[1], __float_as_uint(ms));
+    }
+}
+
 __global__ void pack_kernel(const double *__restrict__ pv, float4 *__restrict__ out, int64_t N) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < N) out[i] = make_float4((float)pv[4 * i], (float)pv[4 * i + 1], (float)pv[4 * i + 2], (float)pv[4 * i + 3]);
@@ -35,7 +73,7 @@ __device__ inline double d64(const double *a, const double *b) {
 
 __global__ __launch_bounds__(BT) void certify_kernel(const float4 *__restrict__ pf, const double *__restrict__ pv,
                                                      const double *__restrict__ wit, int64_t N, double tol,
-                                                     float eps, Cnt *out) {
+                                                     const unsigned *__restrict__ mag, Cnt *out) {
     __shared__ float4 tile[TILE];
     __shared__ unsigned long long red[2][BT];
     const int tid = threadIdx.x;
@@ -53,6 +91,8 @@ __global__ __launch_bounds__(BT) void certify_kernel(const float4 *__restrict__ 
         wcov[k] = false;
     }
     const float ftol = (float)tol;
+    constexpr float U = 5.9604645e-8f;  // float32 unit roundoff
+    const float eps = 2.0f * U * (32.0f * __uint_as_float(mag[0]) + 6.0f * __uint_as_float(mag[1]));
     for (int64_t t0 = 0; t0 < N; t0 += TILE) {
         const int cnt = (int)min((int64_t)TILE, N - t0);
         __syncthreads();
@@ -112,6 +152,7 @@ size_t certify_ws(int64_t N, const sdfi_options &) {
     Carver c(nullptr, 0, true);
     c.take<float4>(N > 0 ? N : 1);
     c.take<Cnt>(1);
+    c.take<unsigned>(2);
     return c.used + 256;
 }
 
@@ -119,18 +160,18 @@ sdfi_status run_certify(const double *pv, const double *wit, int64_t N, int64_t 
                         Carver &ws, const sdfi_options &o, hipStream_t st) {
     float4 *pf = ws.take<float4>(N > 0 ? N : 1);
     Cnt *cnt = ws.take<Cnt>(1);
+    unsigned *mag = ws.take<unsigned>(2);
     if (!ws.ok()) {
         set_error("workspace too small for the certificate");
         return SDFI_ERR_WORKSPACE;
     }
-    SDFI_HIP(hipMemsetAsync(cnt, 0, sizeof(Cnt), st));
+    mag_init_kernel<<<1, 64, 0, st>>>(mag, cnt);
     if (N > 0) {
+        mag_kernel<<<(unsigned)std::min<int64_t>((N + 255) / 256, 1024), 256, 0, st>>>(pv, wit, N, mag);
         pack_kernel<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(pv, pf, N);
         const int64_t per = (int64_t)BT * RPT;
-        // float32 margin error: < 2e-6 for magnitudes <= 2 (two distances and a
-        // difference of rounded values); screen with 4e-6
         KernelTimer tm("certify", st);
-        certify_kernel<<<(unsigned)((N + per - 1) / per), BT, 0, st>>>(pf, pv, wit, N, o.tol, 4e-6f, cnt);
+        certify_kernel<<<(unsigned)((N + per - 1) / per), BT, 0, st>>>(pf, pv, wit, N, o.tol, mag, cnt);
         tm.stop();
         SDFI_HIP(hipGetLastError());
     }

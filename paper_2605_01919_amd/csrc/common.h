@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
@@ -85,6 +86,16 @@ size_t greedy_ws(int64_t n, int64_t m, const sdfi_options &o);
 size_t rmin_ws(int64_t n, int64_t m, const sdfi_options &o);
 size_t repair_ws(int64_t n, int64_t m, const sdfi_options &o);
 size_t backward_ws(int64_t n, int64_t m);
+
+// Device-side input checks, one read-back: non-finite inputs or an order_in
+// that is not a permutation (SDFI_ERR_INVALID_ARGUMENT); with grid > 0
+// (qgrid > 0) samples (queries) outside their own cell of that grid on
+// [0,1]^3, and with `domain` sample or query points outside the options'
+// domain box (SDFI_ERR_DOMAIN).  `order` may be null.  Synchronises.
+size_t check_ws(int64_t m);
+sdfi_status validate_inputs(const double *samples, int64_t n, const double *queries, int64_t m,
+                            const int64_t *order, int grid, int qgrid, bool domain, void *scratch,
+                            size_t scratch_bytes, const sdfi_options &o, hipStream_t st);
 
 // dense bound sweep used by sdfi_bounds and internally (samples n x 4)
 sdfi_status run_bounds(const double *samples, int64_t n, const double *queries, int64_t m, double *lo,

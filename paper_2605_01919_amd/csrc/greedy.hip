@@ -513,7 +513,8 @@ size_t greedy_ws(int64_t n, int64_t m, const sdfi_options &o) {
     Carver c2(nullptr, 0, true);
     size_t ord = order_ws(n, m, o);
     size_t cert = (o.flags & SDFI_OPT_CERTIFY) ? certify_ws(n + m, o) + 4 * (n + m) * 8 + 3 * (n + m) * 8 + 1024 : 0;
-    return c.used + std::max(ord, cert) + 1024;
+    size_t incheck = (o.flags & SDFI_OPT_INPUT_CHECK) ? certify_ws(n, o) : 0;
+    return c.used + std::max({ord, cert, incheck, check_ws(m)}) + 1024;
 }
 
 sdfi_status run_order(const double *samples, int64_t n, const double *queries, int64_t m, int64_t *order_out,
@@ -567,6 +568,17 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
         return SDFI_ERR_WORKSPACE;
     }
     double t0 = now_ms();
+    char *rest_base = c.base + c.used + 256;
+    const size_t rest_bytes = ws_bytes > c.used + 256 ? ws_bytes - c.used - 256 : 0;
+    // 0. inputs: finite, inside the domain box (Appendix B), grid samples and
+    //    refinement queries where the order is derived, order_in a permutation
+    for (int i = 0; i < ninst; ++i) {
+        const int g = order_in ? 0 : (grids ? grids[i] : o.grid);
+        sdfi_status s = validate_inputs(samples + 4 * soff[i], soff[i + 1] - soff[i], queries + 3 * qoff[i],
+                                        qoff[i + 1] - qoff[i], order_in ? order_in + qoff[i] : nullptr, g, 2 * g,
+                                        true, rest_base, rest_bytes, o, st);
+        if (s != SDFI_OK) return s;
+    }
     // 1. witnesses of the input spheres
     SDFI_HIP(hipMemsetAsync(b.wstat, 0, n + 1, st));
     for (int i = 0; i < ninst; ++i) {
@@ -575,6 +587,9 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
         if (s != SDFI_OK) return s;
     }
     if (o.flags & SDFI_OPT_INPUT_CHECK) {
+        // Prop. 1 on the inputs: every sphere has an uncovered point (the
+        // witness search) and no pair breaks the cone (the certificate's
+        // pairwise count on the samples)
         std::vector<uint8_t> h(n);
         SDFI_HIP(hipMemcpyAsync(h.data(), b.wstat, n, hipMemcpyDeviceToHost, st));
         SDFI_HIP(hipStreamSynchronize(st));
@@ -583,6 +598,19 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
                 set_error("input sample %lld has no uncovered point (Prop. 1 (ii) violated)", (long long)i);
                 return SDFI_ERR_INVALID_INPUT;
             }
+        for (int i = 0; i < ninst; ++i) {
+            Carver cc(rest_base, rest_bytes);
+            int64_t pv = 0, wv = 0;
+            sdfi_status s = run_certify(samples + 4 * soff[i], b.win + 3 * soff[i], soff[i + 1] - soff[i], &pv, &wv,
+                                        cc, o, st);
+            if (s != SDFI_OK) return s;
+            if (pv > 0) {
+                set_error("instance %d: %lld pairs of input samples break the cone |s_x - s_y| <= |p_x - p_y| "
+                          "(opposite-sign spheres intersect or a sphere lies in another's ball, Prop. 1)",
+                          i, (long long)pv);
+                return SDFI_ERR_INVALID_INPUT;
+            }
+        }
     }
     double t1 = now_ms();
     // 2. order

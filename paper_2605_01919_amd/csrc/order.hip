@@ -107,7 +107,7 @@ size_t order_ws(int64_t n, int64_t m, const sdfi_options &o) {
     // instance of at most n samples
     int64_t fine = (int64_t)2 * o.grid;
     int64_t cells = o.grid > 0 ? fine * fine * fine : 8 * n;
-    return sizeof(int) * (size_t)std::max<int64_t>(cells, 1) + 4096;
+    return sizeof(int) * (size_t)std::max<int64_t>(cells, 1) + 4096 + check_ws(0);
 }
 
 sdfi_status run_order(const double *samples, int64_t n, const double *queries, int64_t m, int64_t *order_out,
@@ -184,5 +184,9 @@ extern "C" sdfi_status sdfi_refinement_order(const double *samples, int64_t n, c
         return SDFI_ERR_WORKSPACE;
     }
     Carver c(ws, ws_bytes);
+    char *chk = c.take<char>(check_ws(0));
+    s = validate_inputs(samples, n, queries, queries ? m : 0, nullptr, o.grid, 0, false, chk, check_ws(0), o,
+                        to_hip(stream));
+    if (s != SDFI_OK) return s;
     return run_order(samples, n, queries, m, order_out, c, o, to_hip(stream));
 }

@@ -152,6 +152,7 @@ sdfi_status launch_rmin(const double *pts, const int8_t *force, const double *ke
 
 size_t rmin_ws(int64_t n, int64_t m, const sdfi_options &) {
     Carver c(nullptr, 0, true);
+    c.take<char>(check_ws(0));                    // input checks
     c.take<double>(3 * (n + 1));                  // witnesses
     c.take<uint8_t>(n + 1);                       // status
     c.take<int64_t>((size_t)RGRID * 2 * (n + 1)); // per work-group lists
@@ -161,6 +162,7 @@ size_t rmin_ws(int64_t n, int64_t m, const sdfi_options &) {
 
 size_t repair_ws(int64_t n, int64_t m, const sdfi_options &) {
     Carver c(nullptr, 0, true);
+    c.take<char>(check_ws(0));                    // input checks
     c.take<double>(3 * (n + 1));                  // witnesses of all samples
     c.take<uint8_t>(n + 1);                       // status
     c.take<int64_t>(n + 1);                       // kept indices
@@ -197,10 +199,13 @@ extern "C" sdfi_status sdfi_min_valid_radius(const double *samples, int64_t n, c
     }
     hipStream_t st = to_hip(stream);
     Carver c(ws, ws_bytes);
+    char *chk = c.take<char>(check_ws(0));
     double *W = c.take<double>(3 * (n + 1));
     uint8_t *wst = c.take<uint8_t>(n + 1);
     int64_t *lists = c.take<int64_t>((size_t)RGRID * 2 * (n + 1));
     int32_t *flists = c.take<int32_t>((size_t)RGRID * RW * flist_cap(n));
+    s = validate_inputs(samples, n, queries, m, nullptr, 0, 0, true, chk, check_ws(0), o, st);
+    if (s != SDFI_OK) return s;
     s = run_witnesses(samples, n, W, wst, o, st);
     if (s != SDFI_OK) return s;
     return launch_rmin(queries, nullptr, nullptr, m, samples, W, n, o, values, kind, witness, lists, flists, st);
@@ -222,6 +227,7 @@ extern "C" sdfi_status sdfi_repair(const double *samples, int64_t n, const doubl
     }
     hipStream_t st = to_hip(stream);
     Carver c(ws, ws_bytes);
+    char *chk = c.take<char>(check_ws(0));
     double *W = c.take<double>(3 * (n + 1));
     uint8_t *wst = c.take<uint8_t>(n + 1);
     int64_t *kidx = c.take<int64_t>(n + 1);
@@ -236,6 +242,8 @@ extern "C" sdfi_status sdfi_repair(const double *samples, int64_t n, const doubl
     double *contact = c.take<double>(3 * (n + m + 1));
     int64_t *lists = c.take<int64_t>((size_t)RGRID * 2 * (n + 1));
     int32_t *flists = c.take<int32_t>((size_t)RGRID * RW * flist_cap(n));
+    s = validate_inputs(samples, n, queries, m, nullptr, 0, 0, true, chk, check_ws(0), o, st);
+    if (s != SDFI_OK) return s;
     double t0 = now_ms();
     // 1. fully covered samples (Prop. 1 (ii) fails): no witness against all inputs
     s = run_witnesses(samples, n, W, wst, o, st);
