@@ -340,6 +340,29 @@ static int cmp_lb(const void *x, const void *y)
  * 1 T, 2 D, 3 U; -1 nothing found).  W (nullable, NaN rows allowed) holds
  * known uncovered points; the nearest one on a sigma-sphere bounds the
  * search from above. */
+/* Distance from q to the points of sphere (p, r) outside the open ball
+ * (c, R) (INFINITY if none), taken a hair short.  A point of the sphere is
+ * v = p + r u with |u| = 1; the ball holds the cap u.a > cos_t with a the unit
+ * direction from p to c and cos_t = (r^2 + D^2 - R^2)/(2 r D).  If the
+ * direction g from p to q lies outside that cap, the nearest point is the
+ * radial one (distance |d - r|); otherwise it lies on the cap's rim, where
+ * u.g is largest at cos_t (g.a) + sin_t sqrt(1 - (g.a)^2). */
+static double dist_outside(const double *q, const double *p, double r, const double *c, double R)
+{
+    double d = dist3(q, p), D = dist3(c, p);
+    double foot = fabs(d - r);
+    if (!(R > 0.0) || !(r > 0.0) || !(D > 0.0) || !(d > 0.0)) return foot;
+    if (D + r < R * (1.0 - 1e-12) - 1e-15) return INFINITY;
+    if (!(D < r + R) || !(D + R > r)) return foot;
+    double cos_t = (r * r + D * D - R * R) / (2.0 * r * D);
+    if (!(cos_t > -1.0 && cos_t < 1.0)) return foot;
+    double ga = ((q[0] - p[0]) * (c[0] - p[0]) + (q[1] - p[1]) * (c[1] - p[1]) + (q[2] - p[2]) * (c[2] - p[2])) / (d * D);
+    if (!(ga > cos_t)) return foot;
+    double ug = cos_t * ga + sqrt(fmax(0.0, 1.0 - cos_t * cos_t)) * sqrt(fmax(0.0, 1.0 - ga * ga));
+    double rim = sqrt(fmax(0.0, r * r + d * d - 2.0 * r * d * ug));
+    return fmax(foot, rim * (1.0 - 1e-12) - 1e-15);
+}
+
 int og_min_valid_radius(const double *q, int sigma, const double *P, const double *S, long N, double tol,
                         double tie, const double *W, double *r_out, double *x, long *sphere)
 {
@@ -405,10 +428,14 @@ int og_min_valid_radius(const double *q, int sigma, const double *P, const doubl
         }
     }
     qsort(ord, (size_t)cnt, sizeof(lbidx_t), cmp_lb);
+    /* an uncovered point of sphere i lies outside every other ball, the
+     * deepest one (contour balls shrunk by tie) included */
+    const double Rd = fabs(S[deepest]) - tie;
     for (long k = 0; k < cnt; ++k) {
         if (ord[k].lb >= bound) break;
         long i = ord[k].idx;
         if (i == deepest) continue;
+        if (dist_outside(q, P + 3 * i, fabs(S[i]), P + 3 * deepest, Rd) >= bound) continue;
         kk = og_nearest_uncovered(P + 3 * i, fabs(S[i]), LPc, LSc, LN, q, bound, tie, &d, y);
         if (kk && d < bound) {
             bound = d; kind = kk; *sphere = i;

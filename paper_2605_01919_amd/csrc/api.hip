@@ -95,6 +95,18 @@ void note_count(const char *n, const int64_t *dev, hipStream_t st) {
     g_pcount.push_back(p);
 }
 
+bool timing_enabled() {
+    if (g_no_alloc) return false;
+    std::lock_guard<std::mutex> lk(g_tm);
+    return g_timing;
+}
+
+void add_count(const char *n, int64_t v) {
+    if (g_no_alloc) return;
+    std::lock_guard<std::mutex> lk(g_tm);
+    if (g_timing) g_count[n] += v;
+}
+
 sdfi_status read_options(const sdfi_options *opt, sdfi_options *out) {
     sdfi_default_options(out);
     if (!opt) return SDFI_OK;

@@ -13,6 +13,20 @@ using geom::Cap;
 constexpr int NRAY = 15;  // rays of the minimum valid radius' upper bound
 constexpr int RAYMAX = 16;
 
+// Optional device-clock profile of rmin_block (slots of a counter array,
+// written by thread 0 / lane 0 only): time in the containment scans, the ray
+// bound, the candidate list builds and the sphere searches, and the number
+// of calls, passes, listed candidates, local-set balls and sphere searches.
+enum {
+    RP_T_SCAN = 0, RP_T_RAY, RP_T_LIST, RP_T_SEARCH, RP_CALLS, RP_PASSES, RP_LIST_LEN, RP_LOCAL_LEN, RP_SEARCHES,
+    // sphere searches (geom::lazy_nearest) that end before any cover scan,
+    // right after the first one, and that enter the refinement rounds; rounds
+    // run; searches that reach the exhaustive walk; wave ticks in the first
+    // cover scan and in the rounds
+    RP_LN_EARLY, RP_LN_FIRST, RP_LN_LOOP, RP_LN_ROUNDS, RP_LN_FALLBACK, RP_LN_T_FIRST, RP_LN_T_LOOP,
+    RP_COUNT
+};
+
 template <int NW>
 struct Shared {
     double rd[NW];
@@ -124,6 +138,34 @@ __device__ inline bool better(double d, int nd, double lb, int64_t i, double d2,
     return i < i2;
 }
 
+// Lower bound of the distance from q to the points of sphere (p, r) that lie
+// outside the open ball (pa, Ra) (INFINITY when there are none): every
+// uncovered point of the sphere is such a point.  The points outside the ball
+// are the sphere minus the cap v.u > c (u towards pa, c = (r^2 + D^2 -
+// Ra^2)/(2 r D)); the nearest to q is the radial foot point when it lies
+// outside the cap, else the rim point nearest to q, at distance
+// sqrt(r^2 + d^2 - 2 r d (c g.u + sqrt(1 - c^2) sqrt(1 - (g.u)^2))) with g the
+// direction from p to q.  The result is taken slightly short (relative
+// 1e-12), so rounding never makes it exceed the true distance.
+__device__ inline double dist_outside_ball(const double *q, const double *p, double r, const double *pa, double Ra) {
+#pragma clang fp contract(off)
+    const double g0 = q[0] - p[0], g1 = q[1] - p[1], g2 = q[2] - p[2];
+    const double d = sqrt(g0 * g0 + g1 * g1 + g2 * g2);
+    const double foot = fabs(d - r);
+    const double u0 = pa[0] - p[0], u1 = pa[1] - p[1], u2 = pa[2] - p[2];
+    const double D = sqrt(u0 * u0 + u1 * u1 + u2 * u2);
+    if (!(Ra > 0.0) || !(r > 0.0) || !(D > 0.0) || !(d > 0.0)) return foot;
+    if (D + r < Ra * (1.0 - 1e-12) - 1e-15) return INFINITY;  // the whole sphere is inside the ball
+    if (!(D < r + Ra) || !(D + Ra > r)) return foot;           // the ball misses the sphere
+    const double c = (r * r + D * D - Ra * Ra) / (2.0 * r * D);
+    if (!(c > -1.0 && c < 1.0)) return foot;
+    const double gu = (g0 * u0 + g1 * u1 + g2 * u2) / (d * D);
+    if (!(gu > c)) return foot;                                 // the foot point is outside the ball
+    const double vg = c * gu + sqrt(fmax(0.0, 1.0 - c * c)) * sqrt(fmax(0.0, 1.0 - gu * gu));
+    const double rim = sqrt(fmax(0.0, r * r + d * d - 2.0 * r * d * vg));
+    return fmax(foot, rim * (1.0 - 1e-12) - 1e-15);
+}
+
 // Upper bound of the minimum valid radius from ray exits (see rmin_block);
 // out of line so that its per-ray state does not weigh on the caller's
 // registers.  All threads of the work-group call it.
@@ -213,9 +255,19 @@ template <int NW>
 __device__ inline int rmin_block(const double *q, int sigma, const double *p4, const double *W, int64_t N, double tol,
                                  double tie, int64_t *list, Cap (*kp)[geom::KMAX], int64_t (*kid)[geom::KMAX],
                                  int32_t *flist, int fcap,
-                                 Shared<NW> &S, double *r_out, double *x_out, int64_t *sphere_out) {
+                                 Shared<NW> &S, double *r_out, double *x_out, int64_t *sphere_out,
+                                 unsigned long long *prof = nullptr) {
     const int tid = threadIdx.x;
     const int BS = NW * 64;
+    unsigned long long tmark = (prof && tid == 0) ? wall_clock64() : 0ull;
+    auto lap = [&](int slot) {
+        if (prof && tid == 0) {
+            const unsigned long long t = wall_clock64();
+            prof[slot] += t - tmark;
+            tmark = t;
+        }
+    };
+    if (prof && tid == 0) prof[RP_CALLS] += 1;
     // inside test, deepest sigma ball, and the nearest known contour point
     double depth = -INFINITY, wbest = INFINITY;
     int inside = 0;
@@ -246,6 +298,7 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
         if (fabs(p[3]) - geom::dist3(q, p) == depth) deepest = deepest < c ? deepest : c;
     }
     deepest = bmin_i64(deepest, S);
+    lap(RP_T_SCAN);
     if (deepest == INT64_MAX) return -2;  // no ball attains the depth (only with NaN data): no answer
     const double wbound = isinf(wbest) ? INFINITY : wbest * (1.0 + 1e-12) + 1e-15;
     double bound = wbound, rbound = INFINITY;
@@ -257,6 +310,7 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
     // scan per step; a ray stops once it is past the nearest exit found.
     rbound = ray_bound<NW>(q, sigma, p4, N, tie, deepest, depth, wbound, S);
     bound = fmin(bound, rbound);
+    lap(RP_T_RAY);
     int64_t *lset = list + (N + 1);
     // Both bounds can fall just short of the answer: a cached witness is only
     // uncovered w.r.t. the tol-shrunk balls, and the ray may leave the sigma
@@ -266,8 +320,12 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
     // that size, then to no bound at all; what a pass finds within its bound
     // is exact.
     const double looser = bound + 4e-3;
+    const double *pdeep = p4 + 4 * deepest;
+    const double Rdeep = fabs(pdeep[3]) - tie;  // the contour's balls are shrunk by tie
     for (int pass = 0; pass < 3; ++pass) {
-        // candidate spheres: sigma spheres passing within `bound` of q (deepest first)
+        // candidate spheres: sigma spheres with points outside the deepest ball
+        // within `bound` of q (deepest first): a sphere's uncovered points lie
+        // outside every other ball, the deepest one included
         int64_t len = 0, nl = 0;
         for (int64_t base = 0; base < N; base += BS) {
             int64_t c = base + tid;
@@ -275,7 +333,8 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
             if (c < N) {
                 const double *p = p4 + 4 * c;
                 double d = geom::dist3(q, p);
-                if (c != deepest && sign_class(p[3], tie) == sigma) f = fabs(d - fabs(p[3])) <= bound;
+                if (c != deepest && sign_class(p[3], tie) == sigma && fabs(d - fabs(p[3])) <= bound)
+                    f = dist_outside_ball(q, p, fabs(p[3]), pdeep, Rdeep) <= bound;
                 // the local set: balls that can cover a point within `bound` of q
                 inl = isinf(bound) || d < fabs(p[3]) + bound;
             }
@@ -284,6 +343,12 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
         }
         if (tid == 0) list[0] = deepest;
         ++len;
+        lap(RP_T_LIST);
+        if (prof && tid == 0) {
+            prof[RP_PASSES] += 1;
+            prof[RP_LIST_LEN] += (unsigned long long)len;
+            prof[RP_LOCAL_LEN] += (unsigned long long)nl;
+        }
         Balls L;
         L.p4 = p4;
         L.N = nl;
@@ -308,7 +373,7 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
         int64_t wi = INT64_MAX;
         int wk = 0, wnd = 1;
         double wlow = INFINITY;
-        geom::Holders hold{S.hball, &S.hnext};  // shared by the waves, reset each pass
+        geom::Holders hold{S.hball, &S.hnext, prof ? prof + RP_LN_EARLY : nullptr};  // shared by the waves, reset each pass
         const int w = wid();
         // each wave takes PULL candidates at a time: lanes load them and their
         // lower bounds together, then the survivors are searched in list order
@@ -322,10 +387,11 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
             const int64_t kl = (int64_t)k0 + lane();
             const bool have = lane() < PULL && kl < len;
             const int64_t myi = have ? list[kl] : 0;
-            double mylb = INFINITY;
+            double mylb = INFINITY, myprune = INFINITY;  // tie-break key, pruning bound
             if (have) {
                 const double *pp = p4 + 4 * myi;
                 mylb = fabs(geom::dist3(q, pp) - fabs(pp[3]));
+                myprune = myi == deepest ? mylb : dist_outside_ball(q, pp, fabs(pp[3]), pdeep, Rdeep);
             }
             unsigned long long pending = __ballot(have);
             while (pending) {
@@ -333,7 +399,7 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
                 if (lane() == 0) cb = __hip_atomic_load(&S.bound_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 const double cur = __longlong_as_double((long long)__shfl(cb, 0, 64));  // wave-uniform
                 // prune only clearly worse spheres: exact ties must reach the tie-break
-                pending &= __ballot(!(mylb > cur * (1.0 + 1e-12) + 1e-15));
+                pending &= __ballot(!(myprune > cur * (1.0 + 1e-12) + 1e-15));
                 if (!pending) break;
                 const int src = __ffsll((long long)pending) - 1;
                 pending &= pending - 1ull;
@@ -341,6 +407,7 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
                 const double lbi = __shfl(mylb, src, 64);
                 const double *p = p4 + 4 * i;
                 double d, x[3];
+                if (prof && lane() == 0) atomicAdd(&prof[RP_SEARCHES], 1ull);
                 int kk = geom::lazy_nearest(L, p, fabs(p[3]), q, cur * (1.0 + 1e-12) + 1e-15, kp[w], kid[w],
                                             flist + (int64_t)w * fcap, fcap, &d, x, &hold);
                 if (kk < 0) {
@@ -395,6 +462,7 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
             res = S.wk[bw];
         }
         __syncthreads();
+        lap(RP_T_SEARCH);
         if (numeric) return -2;
         if (res > 0) return res;
         if (isinf(bound)) break;

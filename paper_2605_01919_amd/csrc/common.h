@@ -55,6 +55,12 @@ struct KernelTimer {
 // queued on `st` so far has finished) to the counter `name`.
 void note_count(const char *name, const int64_t *dev, hipStream_t st);
 
+// Whether kernel timing is enabled (and this thread may record).
+bool timing_enabled();
+
+// While timing is enabled: add a host value to the counter `name`.
+void add_count(const char *name, int64_t value);
+
 // Validated copy of the caller's options (defaults when opt == NULL).
 sdfi_status read_options(const sdfi_options *opt, sdfi_options *out);
 

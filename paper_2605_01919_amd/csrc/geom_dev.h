@@ -483,7 +483,8 @@ __device__ inline void wave_cover_list(const Balls &B, const double *o, double r
 // off the rim it was found on) to x.  kp: this wave's LDS scratch (KMAX caps),
 // kid: their ball indices.  hint orders the search only.
 __device__ inline int lazy_exist(const Balls &B0, const double *o, double r, const double *hint, Cap *kp,
-                                 int64_t *kid, int32_t *cl, int ccap, double *x) {
+                                 int64_t *kid, int32_t *cl, int ccap, double *x,
+                                 unsigned long long *walks = nullptr) {
     const int lane = threadIdx.x & 63;
     Balls B = B0;
     if (!(r > 0.0)) {
@@ -627,6 +628,7 @@ __device__ inline int lazy_exist(const Balls &B0, const double *o, double r, con
     // bounded by the list's size ccap: beyond it the search reports a numeric
     // failure.
     // (after compaction every ball of B has a cap and B's own list stands in)
+    if (walks && lane == 0) atomicAdd(walks, 1ull);  // searches that reach the exhaustive walk
     const int ncap = compact ? (int)ball_count(B) : wave_list_caps(B, o, r, cl, ccap);
     if (!compact && ncap > ccap) return ST_NUMERIC;  // the list holds only the first ccap
     const int32_t *lst = compact ? nullptr : cl;
@@ -661,8 +663,9 @@ __device__ inline int lazy_exist(const Balls &B0, const double *o, double r, con
 // lazy_exist kept out of line, for callers whose own code it would bloat (the
 // greedy's candidate check; a nearest search whose q is the sphere's centre)
 __device__ __noinline__ int lazy_exist_call(const Balls &B, const double *o, double r, const double *hint, Cap *kp,
-                                            int64_t *kid, int32_t *cl, int ccap, double *x) {
-    return lazy_exist(B, o, r, hint, kp, kid, cl, ccap, x);
+                                            int64_t *kid, int32_t *cl, int ccap, double *x,
+                                            unsigned long long *walks = nullptr) {
+    return lazy_exist(B, o, r, hint, kp, kid, cl, ccap, x, walks);
 }
 
 // Recently seen balls that held a whole search region (ball indices, -1
@@ -673,6 +676,10 @@ constexpr int NHOLD = 32;
 struct Holders {
     int64_t *h;  // NHOLD entries (LDS)
     int *next;   // ring position (LDS)
+    unsigned long long *prof = nullptr;  // optional search profile: early, first, loop, rounds, fallback, ticks
+    __device__ void note(int k, unsigned long long v) {
+        if (prof && (threadIdx.x & 63) == 0) atomicAdd(&prof[k], v);
+    }
     __device__ void push(int64_t f) {
         if ((threadIdx.x & 63) == 0) {
             const int slot = atomicAdd(next, 1) & (NHOLD - 1);
@@ -685,7 +692,7 @@ struct Holders {
 // bound (strictly less or equal kept: ties are broken by the caller).
 // Returns 0 none, 1 radial foot point (T), 2 rim nearest point (D), 3 rim arc
 // end (U), -1 numeric failure; writes distance and point.
-__device__ inline int lazy_nearest(const Balls &B0, const double *o, double r, const double *q, double bound, Cap *kp,
+__device__ __noinline__ int lazy_nearest(const Balls &B0, const double *o, double r, const double *q, double bound, Cap *kp,
                                    int64_t *kid, int32_t *cl, int ccap, double *dist_out, double *x,
                                    Holders *hold = nullptr) {
     const int lane = threadIdx.x & 63;
@@ -722,7 +729,10 @@ __device__ inline int lazy_nearest(const Balls &B0, const double *o, double r, c
     }
     double v0[3] = {g[0] / gn, g[1] / gn, g[2] / gn};
     double d0 = fabs(gn - r);
-    if (d0 > bound) return 0;
+    if (d0 > bound) {
+        if (hold) hold->note(0, 1);
+        return 0;
+    }
     // a single ball holding every point of the sphere within the bound ends
     // the search; the balls that did so recently (ball indices of B0) are
     // tried on their own first
@@ -738,17 +748,35 @@ __device__ inline int lazy_nearest(const Balls &B0, const double *o, double r, c
                 hit = st == 2 || (st == 1 && region_held(B, ch));
             }
         }
-        if (wor(hit)) return 0;
+        if (wor(hit)) {
+            hold->note(0, 1);
+            return 0;
+        }
     }
     int64_t hnew = INT64_MAX;
+    const unsigned long long t_first = (hold && hold->prof) ? wall_clock64() : 0ull;
     wave_cover(B, o, r, v0, -1, &mx, &arg, &whole, &held, hold ? &hnew : nullptr);
+    if (hold) hold->note(5, wall_clock64() - t_first);
     if (held && hold) hold->push(hnew);
+    if (whole || held || !(mx > COVER_EPS)) {
+        if (hold) hold->note(1, 1);
+    } else if (hold) {
+        hold->note(2, 1);
+    }
     if (whole || held) return 0;
     if (!(mx > COVER_EPS)) {
         for (int j = 0; j < 3; ++j) x[j] = o[j] + r * v0[j];
         *dist_out = d0;
         return 1;
     }
+    const unsigned long long t_loop = (hold && hold->prof) ? wall_clock64() : 0ull;
+    struct LoopTicks {
+        Holders *h;
+        unsigned long long t;
+        __device__ ~LoopTicks() {
+            if (h) h->note(6, wall_clock64() - t);
+        }
+    } loop_ticks{hold, t_loop};
     int k = 1;
     if (lane == 0) {
         kid[0] = arg;
@@ -757,6 +785,7 @@ __device__ inline int lazy_nearest(const Balls &B0, const double *o, double r, c
     wave_sync_lds();
     double lowest = d0;  // every uncovered point is at least this far from q
     for (int round = 0; round < 8 * KMAX; ++round) {
+        if (hold) hold->note(3, 1);
         const SubsetCaps sub{kp, k};
         double cd = INFINITY, cpx = 0.0, cpy = 0.0;
         int ckind = 0, crim = -1;
@@ -847,6 +876,7 @@ __device__ inline int lazy_nearest(const Balls &B0, const double *o, double r, c
     // Fallback: every rim against every listed cap (bounded as in
     // lazy_exist).  When capped, return -1 with the last subset-nearest
     // distance, a lower bound.
+    if (hold) hold->note(4, 1);
     const int ncap = wave_list_caps(B, o, r, cl, ccap);
     if (ncap > ccap) {
         *dist_out = lowest;

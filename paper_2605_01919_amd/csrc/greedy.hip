@@ -36,8 +36,15 @@ constexpr int NW_DEFAULT = 8;
 
 enum {
     C_HI = 0, C_LO, C_ZERO, C_RMIN, C_COINC, C_INFEAS, C_UNRES, C_SEARCH, C_NUMERIC,
+    C_WALKS,  // existence searches that reached the exhaustive walk over all listed caps
     // device wall-clock ticks per sub-phase: bounds, candidates, r_min, record
-    C_T_BOUNDS, C_T_CAND, C_T_RMIN, C_T_RECORD, C_NCOUNT
+    C_T_BOUNDS, C_T_CAND, C_T_RMIN, C_T_RECORD,
+    // finer split of the candidate checks: the cover test of the tangent point,
+    // the new sphere's exact search, the threatened-witness scan, the
+    // re-searches; number of threatened spheres
+    C_T_COVER, C_T_VNEW, C_T_THREAT, C_T_REVAL, C_THREAT_LEN,
+    C_RP0,  // blk::RP_COUNT slots of the minimum valid radius profile
+    C_NCOUNT = C_RP0 + blk::RP_COUNT
 };
 
 struct GInst {
@@ -60,6 +67,7 @@ struct GInst {
     double *pend;            // (n + m) x 3 pending witness updates
     unsigned long long *counts;  // C_NCOUNT
     int64_t n, m;
+    int profile;             // record the finer sub-phase split (while timing is enabled)
 };
 
 template <int NW>
@@ -160,7 +168,8 @@ __device__ void revalidate(const GInst &I, int64_t N, const double *q, double s,
             const double *p = I.CP + 4 * c;
             double x[3], hint[3];
             rim_hint(p, fabs(p[3]), q, fabs(s) - tol, I.CW + 3 * c, hint);
-            int st = geom::lazy_exist(B, p, fabs(p[3]), hint, SH.kp[w], SH.kid[w], I.flist + (int64_t)w * I.fcap, I.fcap, x);
+            int st = geom::lazy_exist_call(B, p, fabs(p[3]), hint, SH.kp[w], SH.kid[w], I.flist + (int64_t)w * I.fcap,
+                                           I.fcap, x, &I.counts[C_WALKS]);
             if (ln == 0) {
                 atomicAdd(&I.counts[C_SEARCH], 1ull);
                 if (st == geom::ST_NUMERIC) atomicAdd(&I.counts[C_NUMERIC], 1ull);
@@ -262,6 +271,14 @@ __global__ __launch_bounds__(NW * 64) void greedy_kernel(const GInst *insts, dou
                     ct[e] = is_hi ? b : a;
                     ck[e] = is_hi ? SDFI_KIND_HI : SDFI_KIND_LO;
                 }
+                unsigned long long t_sub = (tid == 0 && I.profile) ? wall_clock64() : 0ull;
+                auto sub = [&](int slot) {
+                    if (tid == 0 && I.profile) {
+                        const unsigned long long t = wall_clock64();
+                        I.counts[slot] += t - t_sub;
+                        t_sub = t;
+                    }
+                };
                 for (int e = 0; e < 2 && !accepted; ++e) {
                     if (!in_domain(cw[e], dlo, dhi, tol)) continue;
                     const double s = cs[e], r = fabs(s);
@@ -272,6 +289,7 @@ __global__ __launch_bounds__(NW * 64) void greedy_kernel(const GInst *insts, dou
                         if (geom::dist3(cw[e], p) < fabs(p[3]) - tol) cov = 1;
                     }
                     cov = blk::bor(cov, SH.S);
+                    sub(C_T_COVER);
                     double nw[3] = {cw[e][0], cw[e][1], cw[e][2]};
                     if (cov) {
                         if (w == 0) {
@@ -285,7 +303,8 @@ __global__ __launch_bounds__(NW * 64) void greedy_kernel(const GInst *insts, dou
                             B.idx = nullptr;
         B.use_region = 0;
                             double x[3];
-                            int st = geom::lazy_exist(B, q, r, cw[e], SH.kp[0], SH.kid[0], I.flist, I.fcap, x);
+                            int st = geom::lazy_exist_call(B, q, r, cw[e], SH.kp[0], SH.kid[0], I.flist, I.fcap, x,
+                                                           &I.counts[C_WALKS]);
                             if (ln == 0) {
                                 SH.status = st;
                                 SH.x[0] = x[0];
@@ -301,14 +320,18 @@ __global__ __launch_bounds__(NW * 64) void greedy_kernel(const GInst *insts, dou
                         nw[1] = SH.x[1];
                         nw[2] = SH.x[2];
                         __syncthreads();
+                        sub(C_T_VNEW);
                         if (st != geom::ST_FOUND) continue;
                     }
                     // existing spheres whose witness lies in the new open (shrunk) ball
                     nthr = threatened(I, N, q, r - tol, n, m, SH);
+                    sub(C_T_THREAT);
+                    if (tid == 0 && I.profile) I.counts[C_THREAT_LEN] += (unsigned long long)nthr;
                     revalidate(I, N, q, s, nthr, tol, SH, false);
                     __syncthreads();
                     int failed = SH.fail;
                     __syncthreads();
+                    sub(C_T_REVAL);
                     if (failed) continue;
                     accepted = 1;
                     val = s;
@@ -334,8 +357,8 @@ __global__ __launch_bounds__(NW * 64) void greedy_kernel(const GInst *insts, dou
                         int sigma = lo > tol ? 1 : -1;
                         double rr, x[3];
                         int64_t sph;
-                        int kk = blk::rmin_block<NW>(q, sigma, I.CP, I.CW, N, tol, tie, I.list, SH.kp, SH.kid, I.flist, I.fcap, SH.S,
-                                                     &rr, x, &sph);
+                        int kk = blk::rmin_block<NW>(q, sigma, I.CP, I.CW, N, tol, tie, I.list, SH.kp, SH.kid, I.flist,
+                                                     I.fcap, SH.S, &rr, x, &sph, I.profile ? I.counts + C_RP0 : nullptr);
                         if (kk == -2 && tid == 0) atomicAdd(&I.counts[C_NUMERIC], 1ull);
                         if (kk > 0) {
                             val = sigma * rr;
@@ -659,6 +682,7 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
         g.flist = b.flist + fpos;
         fpos += (int64_t)nw * g.fcap;
         g.counts = b.counts + C_NCOUNT * i;
+        g.profile = timing_enabled() ? 1 : 0;
         g.n = ni;
         g.m = mi;
         cpos += ni + mi;
@@ -701,6 +725,23 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
             for (int ph = 0; ph < 4; ++ph) report->ms_phase[4 + ph] += cc[C_T_BOUNDS + ph] / wall_khz;
         }
         report->pairs_evaluated = pairs;
+        // the finer split goes to the named work counters (while timing is on)
+        static const char *names[C_NCOUNT - C_T_COVER] = {
+            "greedy_cover_ticks", "greedy_vnew_ticks", "greedy_threat_ticks", "greedy_reval_ticks",
+            "greedy_threatened", "rmin_scan_ticks", "rmin_ray_ticks", "rmin_list_ticks", "rmin_search_ticks",
+            "rmin_calls", "rmin_passes", "rmin_list_len", "rmin_local_len", "rmin_searches", "ln_early", "ln_first",
+            "ln_loop", "ln_rounds", "ln_fallback", "ln_first_ticks", "ln_loop_ticks"};
+        for (int k = C_T_COVER; k < C_NCOUNT; ++k) {
+            unsigned long long tot = 0;
+            for (int i = 0; i < ninst; ++i) tot += cnt[C_NCOUNT * i + k];
+            add_count(names[k - C_T_COVER], (int64_t)tot);
+        }
+        add_count("wall_clock_khz", (int64_t)wall_khz);
+        {
+            unsigned long long tot = 0;
+            for (int i = 0; i < ninst; ++i) tot += cnt[C_NCOUNT * i + C_WALKS];
+            add_count("exist_walks", (int64_t)tot);
+        }
         report->ms_phase[0] = t2 - t1;
         report->ms_phase[1] = t1 - t0;
         report->ms_phase[2] = t3 - t2;

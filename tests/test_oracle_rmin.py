@@ -89,3 +89,33 @@ def test_monte_carlo_upper_bound():
         if unc.any():
             best = min(best, dist(X[unc], q).min())
     assert r <= best + 1e-12 and best - r < 0.02
+
+
+def test_c_radius_search_equals_numpy_definition():
+    # the C search skips spheres whose part outside the deepest ball is beyond
+    # the bound; the NumPy restatement tries every sphere best first: the two
+    # must agree on random ball unions (both signs) and scattered points
+    from oracle import fastgeom, spheres  # noqa: F401
+    from oracle import rmin as RM
+    from oracle import geom as G
+    rng = np.random.default_rng(31)
+    checked = 0
+    for trial in range(40):
+        k = int(rng.integers(6, 14))
+        P = rng.uniform(0.2, 0.8, (k, 3))
+        S = rng.uniform(0.08, 0.25, k) * (1 if trial % 2 == 0 else -1)
+        sigma = 1 if trial % 2 == 0 else -1
+        for q in rng.uniform(0.2, 0.8, (6, 3)):
+            old = G.USE_C
+            try:
+                G.USE_C = True
+                a = RM.min_valid_radius(q, sigma, P, S)
+                G.USE_C = False
+                b = RM.min_valid_radius(q, sigma, P, S)
+            finally:
+                G.USE_C = old
+            assert (a[3] == -1) == (b[3] == -1)
+            if a[3] >= 0:
+                assert abs(a[0] - b[0]) <= 1e-12, (trial, a, b)
+                checked += 1
+    assert checked > 60
