@@ -2,6 +2,7 @@
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-greedy] [--no-batched]
                 [--no-repair] [--copy-bytes N]
+python bench.py --csg N [--save OUT.npz]    (the repair workload on an N^3 grid only, timed in parts)
 
 Timed step (the JSON line's `value`): the dense query x sample bound
 reduction (Sec. 4.3 cone bounds with argmin/argmax, float32 sweep and float64
@@ -124,6 +125,67 @@ def wall(fn):
     return out, time.perf_counter() - t0
 
 
+def measure_csg(grid=96, save=None):
+    """The pseudo-SDF repair workload (CSG samples on a grid^3 grid; at 96 the
+    full recipe with 400 000 scattered extension queries, at smaller grids the
+    query count scaled by (grid/96)^3), timed in parts so that no single GPU
+    call runs for minutes: (1) sdfi_repair on the samples (witness of every sample, removal
+    of the fully covered ones, minimum valid radius of the removed points);
+    (2) the extension queries' minimum valid radius against the kept samples
+    (the same values the repair gives them), in chunks of 50 000 through
+    sdfi_min_valid_radius, whose own witness pass over the kept samples is
+    timed apart and not counted.  Kernel times come from the library's HIP
+    event timers on the launch stream.  Prints one JSON line."""
+    import torch
+    from paper_2605_01919_amd import sdfi
+    from sdfgen import configs
+    dev = torch.device("cuda:0")
+    half = int(round(200000 * (grid / 96) ** 3))
+    w = configs.csg(grid, uniform_queries=half, near_queries=half)
+    samples = torch.tensor(np.c_[w.points, w.values], device=dev)
+    progress(f"csg{grid}: {w.n} samples, {w.m} queries generated")
+    sdfi.timing(True)
+    (rv, removed, _, kind, rep), t_rep = wall(lambda: sdfi.repair(samples))
+    kt = sdfi.timing_read()
+    sdfi.timing(False)
+    progress(f"repair of the samples: {t_rep:.1f} s, {int(rep['n_removed'])} removed; witness kernel "
+             f"{kt['witness'][0]:.0f} ms, minimum radius of removed points {kt['rmin'][0]:.0f} ms")
+    keep = removed == 0
+    base = samples[keep].contiguous()
+    q_ms = 0.0
+    q_wall = 0.0
+    qkinds = []
+    qvals = []
+    for c0 in range(0, w.m, 50000):
+        q = torch.tensor(w.queries[c0:c0 + 50000], device=dev)
+        sdfi.timing(True)
+        (val, k, _), tq = wall(lambda: sdfi.min_valid_radius(base, q))
+        kq = sdfi.timing_read()
+        sdfi.timing(False)
+        q_ms += kq["rmin"][0]
+        q_wall += tq - kq["witness"][0] * 1e-3
+        qkinds.append(k.cpu().numpy())
+        qvals.append(val.cpu().numpy())
+        progress(f"extension queries {c0 + len(q)}/{w.m}: radius kernel {kq['rmin'][0]:.0f} ms")
+    qk = np.concatenate(qkinds)
+    total_s = t_rep + q_wall
+    out = {"workload": f"csg{grid}: CSG pseudo-SDF of 16 primitives, {grid}^3 samples + {w.m} scattered queries "
+                       "(half uniform, half near the zero set)",
+           "samples": w.n, "queries": w.m, "removed": int(rep["n_removed"]),
+           "repair_samples_s": round(t_rep, 3), "witness_kernel_ms": round(kt["witness"][0], 1),
+           "removed_radius_kernel_ms": round(kt["rmin"][0], 1), "query_radius_kernel_ms": round(q_ms, 1),
+           "total_s": round(total_s, 3), "points_per_s": round((int(rep["n_removed"]) + w.m) / total_s, 1),
+           "query_kinds": {int(a): int(b) for a, b in zip(*np.unique(qk, return_counts=True))},
+           "unresolved": int((qk == 255).sum() + (kind.cpu().numpy() == 255).sum())}
+    if save:
+        rng = np.random.default_rng(3003)
+        qi = np.sort(rng.choice(w.m, 256, replace=False))
+        si = np.sort(rng.choice(w.n, 512, replace=False))
+        np.savez(save, P=w.points, S=w.values, Q=w.queries[qi], qidx=qi, qvals=np.concatenate(qvals)[qi],
+                 qkind=qk[qi], sidx=si, removed=removed.cpu().numpy(), repaired=rv.cpu().numpy())
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,12 +196,19 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-repair", action="store_true")
     ap.add_argument("--copy-bytes", type=int, default=0)
+    ap.add_argument("--csg", type=int, default=0,
+                    help="only time the pseudo-SDF repair workload on a CSG^3 grid in parts (96: the full recipe)")
+    ap.add_argument("--save", default=None, help="with --csg: save a seeded sample of the outputs (npz)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the hot path runs on a "
               "single MI355X (how it would shard across GPUs is described in the design notes)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.csg:
+        measure_csg(args.csg, args.save)
+        return
 
     import torch
     from paper_2605_01919_amd import sdfi

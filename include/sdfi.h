@@ -96,7 +96,9 @@ typedef struct {
     int32_t grid;          /* input grid resolution N (samples at the cell centres of an
                               N^3 grid on [0,1]^3, x fastest), 0 = scattered samples */
     int32_t block_size;    /* threads per work-group of the greedy kernels: 256 or 512
-                              (4 or 8 wavefronts per instance), 0 = 512 */
+                              (4 or 8 wavefronts per instance), 0 = 512, or 256 when a
+                              batched launch has more instances than resident
+                              512-thread work-groups */
     uint32_t flags;        /* SDFI_OPT_* */
 } sdfi_options;
 

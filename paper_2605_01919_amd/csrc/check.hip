@@ -5,6 +5,8 @@
 // of the grid the refinement order assumes (Sec. 4.1), and caller orders that
 // are not permutations.  Each check runs on the device and leaves a few flag
 // words that the host reads back once.
+#include <vector>
+
 #include "common.h"
 
 namespace sdfi {
@@ -81,62 +83,83 @@ __global__ void perm_count_kernel(const int64_t *__restrict__ order, int64_t m, 
 
 }  // namespace
 
-size_t check_ws(int64_t m) { return sizeof(unsigned) * (size_t)(m + 64) + 512; }
+size_t check_ws(int64_t m, int64_t njobs) {
+    return sizeof(unsigned) * (size_t)(m + 64 * ((njobs + 63) / 64)) + 512;
+}
 
-sdfi_status validate_inputs(const double *samples, int64_t n, const double *queries, int64_t m,
-                            const int64_t *order, int grid, int qgrid, bool domain, void *scratch,
-                            size_t scratch_bytes,
-                            const sdfi_options &o, hipStream_t st) {
-    if (scratch_bytes < check_ws(order ? m : 0)) {
+sdfi_status validate_jobs(const CheckJob *jobs, int njobs, bool domain, void *scratch, size_t scratch_bytes,
+                          const sdfi_options &o, hipStream_t st) {
+    int64_t mtot = 0;
+    for (int j = 0; j < njobs; ++j)
+        if (jobs[j].order) mtot += jobs[j].m;
+    if (njobs <= 0) return SDFI_OK;
+    if (scratch_bytes < check_ws(mtot, njobs)) {
         set_error("workspace too small for the input checks");
         return SDFI_ERR_WORKSPACE;
     }
+    // one flag word per job, then the permutation counts of the jobs with an order
     unsigned *flag = static_cast<unsigned *>(scratch);
-    unsigned *seen = flag + 64;
-    zero_u32_kernel<<<1, 64, 0, st>>>(flag, 1);
+    unsigned *seen = flag + 64 * ((njobs + 63) / 64);
+    zero_u32_kernel<<<(njobs + 255) / 256, 256, 0, st>>>(flag, njobs);
+    if (mtot > 0) zero_u32_kernel<<<(unsigned)((mtot + 255) / 256), 256, 0, st>>>(seen, mtot);
     Box box;
     for (int k = 0; k < 3; ++k) {
         // without the domain check the box is unbounded and only the other tests run
         box.lo[k] = domain ? o.domain_lo[k] : -INFINITY;
         box.hi[k] = domain ? o.domain_hi[k] : INFINITY;
     }
-    const int64_t tot = n + m;
-    if (tot > 0) {
-        const unsigned blocks = (unsigned)std::min<int64_t>((tot + 255) / 256, 2048);
-        scan_kernel<<<blocks, 256, 0, st>>>(samples, n, queries, m, box, o.tol, grid, qgrid, flag);
-    }
-    if (order && m > 0) {
-        const unsigned blocks = (unsigned)((m + 255) / 256);
-        zero_u32_kernel<<<blocks, 256, 0, st>>>(seen, m);
-        perm_count_kernel<<<blocks, 256, 0, st>>>(order, m, seen, flag);
+    int64_t spos = 0;
+    for (int j = 0; j < njobs; ++j) {
+        const CheckJob &J = jobs[j];
+        const int64_t tot = J.n + J.m;
+        if (tot > 0) {
+            const unsigned blocks = (unsigned)std::min<int64_t>((tot + 255) / 256, 2048);
+            scan_kernel<<<blocks, 256, 0, st>>>(J.samples, J.n, J.queries, J.m, box, o.tol, J.grid, J.qgrid,
+                                                flag + j);
+        }
+        if (J.order && J.m > 0) {
+            perm_count_kernel<<<(unsigned)((J.m + 255) / 256), 256, 0, st>>>(J.order, J.m, seen + spos, flag + j);
+            spos += J.m;
+        }
     }
     SDFI_HIP(hipGetLastError());
-    unsigned h = 0;
-    SDFI_HIP(hipMemcpyAsync(&h, flag, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+    std::vector<unsigned> h(njobs);
+    SDFI_HIP(hipMemcpyAsync(h.data(), flag, sizeof(unsigned) * njobs, hipMemcpyDeviceToHost, st));
     SDFI_HIP(hipStreamSynchronize(st));
-    if (h & BAD_NONFINITE) {
-        set_error("an input coordinate or value is NaN or infinite");
-        return SDFI_ERR_INVALID_ARGUMENT;
-    }
-    if (h & (BAD_PERM_RANGE | BAD_PERM_REPEAT)) {
-        set_error("order_in is not a permutation of [0, m): %s",
-                  (h & BAD_PERM_RANGE) ? "an entry lies outside [0, m)" : "an entry is repeated");
-        return SDFI_ERR_INVALID_ARGUMENT;
-    }
-    if (h & BAD_GRID) {
-        set_error("the samples (queries) do not lie in the cells of the %d^3 (%d^3) grid on [0,1]^3, x fastest",
-                  grid, qgrid);
-        return SDFI_ERR_DOMAIN;
-    }
-    if (h & BAD_SAMPLE_DOMAIN) {
-        set_error("a sample point lies outside the domain box (Appendix B considers only its points)");
-        return SDFI_ERR_DOMAIN;
-    }
-    if (h & BAD_POINT_DOMAIN) {
-        set_error("a query point lies outside the domain box");
-        return SDFI_ERR_DOMAIN;
+    for (int j = 0; j < njobs; ++j) {
+        char where[48] = "";
+        if (njobs > 1) snprintf(where, sizeof where, "instance %d: ", j);
+        if (h[j] & BAD_NONFINITE) {
+            set_error("%san input coordinate or value is NaN or infinite", where);
+            return SDFI_ERR_INVALID_ARGUMENT;
+        }
+        if (h[j] & (BAD_PERM_RANGE | BAD_PERM_REPEAT)) {
+            set_error("%sorder_in is not a permutation of [0, m): %s", where,
+                      (h[j] & BAD_PERM_RANGE) ? "an entry lies outside [0, m)" : "an entry is repeated");
+            return SDFI_ERR_INVALID_ARGUMENT;
+        }
+        if (h[j] & BAD_GRID) {
+            set_error("%sthe samples (queries) do not lie in the cells of the %d^3 (%d^3) grid on [0,1]^3, x fastest",
+                      where, jobs[j].grid, jobs[j].qgrid);
+            return SDFI_ERR_DOMAIN;
+        }
+        if (h[j] & BAD_SAMPLE_DOMAIN) {
+            set_error("%sa sample point lies outside the domain box (Appendix B considers only its points)", where);
+            return SDFI_ERR_DOMAIN;
+        }
+        if (h[j] & BAD_POINT_DOMAIN) {
+            set_error("%sa query point lies outside the domain box", where);
+            return SDFI_ERR_DOMAIN;
+        }
     }
     return SDFI_OK;
+}
+
+sdfi_status validate_inputs(const double *samples, int64_t n, const double *queries, int64_t m,
+                            const int64_t *order, int grid, int qgrid, bool domain, void *scratch,
+                            size_t scratch_bytes, const sdfi_options &o, hipStream_t st) {
+    CheckJob J{samples, n, queries, m, order, grid, qgrid};
+    return validate_jobs(&J, 1, domain, scratch, scratch_bytes, o, st);
 }
 
 }  // namespace sdfi

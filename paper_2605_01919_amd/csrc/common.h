@@ -98,10 +98,28 @@ size_t backward_ws(int64_t n, int64_t m);
 // (qgrid > 0) samples (queries) outside their own cell of that grid on
 // [0,1]^3, and with `domain` sample or query points outside the options'
 // domain box (SDFI_ERR_DOMAIN).  `order` may be null.  Synchronises.
-size_t check_ws(int64_t m);
+size_t check_ws(int64_t m, int64_t njobs = 1);
 sdfi_status validate_inputs(const double *samples, int64_t n, const double *queries, int64_t m,
                             const int64_t *order, int grid, int qgrid, bool domain, void *scratch,
                             size_t scratch_bytes, const sdfi_options &o, hipStream_t st);
+// The same checks for many input sets (one flag word each, one read-back);
+// errors name the failing job when there are several.  `order` of a job may
+// be null; check_ws(total m of the jobs with an order, njobs) bytes.
+struct CheckJob {
+    const double *samples;
+    int64_t n;
+    const double *queries;
+    int64_t m;
+    const int64_t *order;
+    int grid, qgrid;
+};
+sdfi_status validate_jobs(const CheckJob *jobs, int njobs, bool domain, void *scratch, size_t scratch_bytes,
+                          const sdfi_options &o, hipStream_t st);
+
+// One uncovered point per sample (witness kernel).  With seg (device, nseg + 1
+// offsets) the rows form independent sets, each tested against itself only.
+sdfi_status run_witnesses(const double *samples, int64_t n, double *w, uint8_t *st, const sdfi_options &o,
+                          hipStream_t s, const int64_t *seg = nullptr, int nseg = 1);
 
 // dense bound sweep used by sdfi_bounds and internally (samples n x 4)
 sdfi_status run_bounds(const double *samples, int64_t n, const double *queries, int64_t m, double *lo,

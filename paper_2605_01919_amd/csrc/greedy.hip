@@ -21,6 +21,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "block_dev.h"
@@ -440,14 +442,32 @@ __global__ __launch_bounds__(NW * 64) void greedy_kernel(const GInst *insts, dou
             for (int jj = 0; jj < 3; ++jj) I.sample_witness[3 * c + jj] = I.CW[3 * c + jj];
 }
 
-// one wavefront per sample: an uncovered point of its sphere, or none
-__global__ __launch_bounds__(256) void witness_kernel(const double *p4, int64_t n, double tol, double tie,
-                                                      double *wout, uint8_t *status) {
+// One wavefront per sample: an uncovered point of its sphere, or none.  The
+// rows [0, n) of p4 form nseg independent sets [seg[k], seg[k+1]) (seg null:
+// one set); a sample's sphere is tested against its own set only.
+__global__ __launch_bounds__(256) void witness_kernel(const double *p4_all, int64_t n, const int64_t *seg, int nseg,
+                                                      double tol, double tie, double *wout_all, uint8_t *status_all) {
     __shared__ geom::Cap kp[4][geom::KMAX];
     __shared__ int64_t kid[4][geom::KMAX];
     __shared__ int32_t cl[4][geom::FALLBACK_LDS];
     const int w = threadIdx.x >> 6, ln = threadIdx.x & 63;
-    for (int64_t i = (int64_t)blockIdx.x * 4 + w; i < n; i += (int64_t)gridDim.x * 4) {
+    for (int64_t ig = (int64_t)blockIdx.x * 4 + w; ig < n; ig += (int64_t)gridDim.x * 4) {
+        // the set holding row ig (binary search over the segment starts)
+        int64_t s0 = 0, s1 = n;
+        if (seg) {
+            int lo = 0, hi = nseg - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (seg[mid] <= ig) lo = mid;
+                else hi = mid - 1;
+            }
+            s0 = seg[lo];
+            s1 = seg[lo + 1];
+        }
+        const double *p4 = p4_all + 4 * s0;
+        const int64_t i = ig - s0, n = s1 - s0;
+        double *wout = wout_all + 3 * s0;
+        uint8_t *status = status_all + s0;
         const double *pi = p4 + 4 * i;
         int sg = blk::sign_class(pi[3], tie);
         double sg1 = sg != 0 ? (double)sg : 1.0;
@@ -492,11 +512,40 @@ struct GBufs {
     uint8_t *wstat;
     unsigned long long *counts;
     int64_t *order;
+    int64_t *seg;
     GInst *inst;
 };
 
 // wavefronts per greedy work-group for these options
-int greedy_waves(const sdfi_options &o) { return o.block_size == 256 ? 4 : NW_DEFAULT; }
+// Work-groups of the greedy kernel with nw waves that the current device
+// keeps resident at once (occupancy x compute units), looked up once per
+// device.
+int resident_groups(int nw) {
+    static std::mutex mu;
+    static std::map<std::pair<int, int>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find({dev, nw});
+    if (it != cache.end()) return it->second;
+    int per_cu = 0, cus = 0;
+    hipError_t e = nw == 4 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, greedy_kernel<4>, 256, 0)
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, greedy_kernel<NW_DEFAULT>,
+                                                                          NW_DEFAULT * 64, 0);
+    if (e != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return cache[{dev, nw}] = per_cu * cus;
+}
+
+// Wavefronts per greedy work-group.  block_size 256 or 512 fixes it; 0 picks
+// 8 waves while every instance of the launch can hold a resident work-group
+// of 8 waves, else 4 waves, which keeps more instances in flight.
+int greedy_waves(const sdfi_options &o, int ninst = 1) {
+    if (o.block_size == 256) return 4;
+    if (o.block_size == 512 || ninst <= 1) return NW_DEFAULT;
+    const int slots = resident_groups(NW_DEFAULT);
+    return slots > 0 && ninst > slots ? 4 : NW_DEFAULT;
+}
 
 GBufs carve_greedy(Carver &c, int64_t n, int64_t m, int ninst, int nw) {
     GBufs b;
@@ -511,6 +560,7 @@ GBufs carve_greedy(Carver &c, int64_t n, int64_t m, int ninst, int nw) {
     b.wstat = c.take<uint8_t>(n + 1);
     b.counts = c.take<unsigned long long>(C_NCOUNT * ninst);
     b.order = c.take<int64_t>(m + 1);
+    b.seg = c.take<int64_t>(ninst + 1);
     b.inst = c.take<GInst>(ninst);
     return b;
 }
@@ -520,11 +570,11 @@ GBufs carve_greedy(Carver &c, int64_t n, int64_t m, int ninst, int nw) {
 size_t witness_ws(int64_t, const sdfi_options &) { return 256; }
 
 sdfi_status run_witnesses(const double *samples, int64_t n, double *w, uint8_t *st, const sdfi_options &o,
-                          hipStream_t s) {
+                          hipStream_t s, const int64_t *seg, int nseg) {
     if (n == 0) return SDFI_OK;
     int blocks = (int)std::min<int64_t>((n + 3) / 4, 4096);
     KernelTimer tm("witness", s);
-    witness_kernel<<<blocks, 256, 0, s>>>(samples, n, o.tol, o.tie_tol, w, st);
+    witness_kernel<<<blocks, 256, 0, s>>>(samples, n, seg, nseg, o.tol, o.tie_tol, w, st);
     tm.stop();
     SDFI_HIP(hipGetLastError());
     return SDFI_OK;
@@ -542,6 +592,8 @@ size_t greedy_ws(int64_t n, int64_t m, const sdfi_options &o) {
 
 sdfi_status run_order(const double *samples, int64_t n, const double *queries, int64_t m, int64_t *order_out,
                       Carver &ws, const sdfi_options &o, hipStream_t st);
+sdfi_status run_order_batched(int ninst, const int64_t *soff, const int32_t *grids, const double *samples,
+                              int64_t *order_out, Carver &ws, const sdfi_options &o, hipStream_t st);
 
 static double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -584,7 +636,7 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
                                  const sdfi_options &o, hipStream_t st) {
     const int64_t n = soff[ninst], m = qoff[ninst];
     Carver c(ws, ws_bytes);
-    const int nw = greedy_waves(o);
+    const int nw = greedy_waves(o, ninst);
     GBufs b = carve_greedy(c, n + ninst, m, ninst, nw);
     if (!c.ok()) {
         set_error("workspace too small for the greedy interpolation");
@@ -594,19 +646,28 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
     char *rest_base = c.base + c.used + 256;
     const size_t rest_bytes = ws_bytes > c.used + 256 ? ws_bytes - c.used - 256 : 0;
     // 0. inputs: finite, inside the domain box (Appendix B), grid samples and
-    //    refinement queries where the order is derived, order_in a permutation
-    for (int i = 0; i < ninst; ++i) {
-        const int g = order_in ? 0 : (grids ? grids[i] : o.grid);
-        sdfi_status s = validate_inputs(samples + 4 * soff[i], soff[i + 1] - soff[i], queries + 3 * qoff[i],
-                                        qoff[i + 1] - qoff[i], order_in ? order_in + qoff[i] : nullptr, g, 2 * g,
-                                        true, rest_base, rest_bytes, o, st);
+    //    refinement queries where the order is derived, order_in a permutation;
+    //    all instances checked together, one read-back
+    {
+        std::vector<CheckJob> jobs(ninst);
+        for (int i = 0; i < ninst; ++i) {
+            const int g = order_in ? 0 : (grids ? grids[i] : o.grid);
+            jobs[i] = CheckJob{samples + 4 * soff[i], soff[i + 1] - soff[i], queries + 3 * qoff[i],
+                               qoff[i + 1] - qoff[i], order_in ? order_in + qoff[i] : nullptr, g, 2 * g};
+        }
+        sdfi_status s = validate_jobs(jobs.data(), ninst, true, rest_base, rest_bytes, o, st);
         if (s != SDFI_OK) return s;
     }
-    // 1. witnesses of the input spheres
+    // 1. witnesses of the input spheres, each instance against its own
+    //    samples, one launch
     SDFI_HIP(hipMemsetAsync(b.wstat, 0, n + 1, st));
-    for (int i = 0; i < ninst; ++i) {
-        sdfi_status s = run_witnesses(samples + 4 * soff[i], soff[i + 1] - soff[i], b.win + 3 * soff[i],
-                                      b.wstat + soff[i], o, st);
+    {
+        const int64_t *seg = nullptr;
+        if (ninst > 1) {
+            SDFI_HIP(hipMemcpyAsync(b.seg, soff, sizeof(int64_t) * (ninst + 1), hipMemcpyHostToDevice, st));
+            seg = b.seg;
+        }
+        sdfi_status s = run_witnesses(samples, n, b.win, b.wstat, o, st, seg, ninst);
         if (s != SDFI_OK) return s;
     }
     if (o.flags & SDFI_OPT_INPUT_CHECK) {
@@ -638,7 +699,12 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
     double t1 = now_ms();
     // 2. order
     const int64_t *ord = order_in;
-    if (!ord) {
+    if (!ord && ninst > 1) {
+        Carver rest(rest_base, rest_bytes);
+        sdfi_status s = run_order_batched(ninst, soff, grids, samples, b.order, rest, o, st);
+        if (s != SDFI_OK) return s;
+        ord = b.order;
+    } else if (!ord) {
         for (int i = 0; i < ninst; ++i) {
             sdfi_options oi = o;
             oi.grid = grids ? grids[i] : o.grid;
@@ -687,6 +753,12 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
         g.m = mi;
         cpos += ni + mi;
     }
+    // longest first: work-groups start roughly in launch order, so the
+    // instances with the most pairs to scan (n m + m^2 / 2) start earliest and
+    // the short ones fill in behind them
+    std::stable_sort(hi.begin(), hi.end(), [](const GInst &x, const GInst &y) {
+        return x.n * x.m + x.m * x.m / 2 > y.n * y.m + y.m * y.m / 2;
+    });
     SDFI_HIP(hipMemcpyAsync(b.inst, hi.data(), sizeof(GInst) * ninst, hipMemcpyHostToDevice, st));
     KernelTimer tm("greedy", st);
     if (nw == 4)
@@ -737,6 +809,16 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
             add_count(names[k - C_T_COVER], (int64_t)tot);
         }
         add_count("wall_clock_khz", (int64_t)wall_khz);
+        {
+            // the longest instance's device time (bounds + candidates + r_min + record)
+            unsigned long long mx = 0;
+            for (int i = 0; i < ninst; ++i) {
+                unsigned long long t = 0;
+                for (int ph = 0; ph < 4; ++ph) t += cnt[C_NCOUNT * i + C_T_BOUNDS + ph];
+                mx = std::max(mx, t);
+            }
+            add_count("greedy_instance_max_ticks", (int64_t)mx);
+        }
         {
             unsigned long long tot = 0;
             for (int i = 0; i < ninst; ++i) tot += cnt[C_NCOUNT * i + C_WALKS];

@@ -14,13 +14,12 @@ namespace {
 
 constexpr int SUB = 8;
 
-// One work-group of 512 threads per cell of a res^3 grid on [0,1]^3; thread t
-// tests sub-point ((t%8 + 0.5)/8, ...) against the balls, starting with the
-// sample of the input-grid cell (resolution N) that holds it.
-__global__ __launch_bounds__(512) void covered_kernel(const double *__restrict__ p4, int64_t n, int N, int res,
-                                                      int64_t cell0, double tol, int *__restrict__ counts) {
-    __shared__ int red[8];
-    const int64_t cell = cell0 + blockIdx.x;
+// Covered sub-points of one cell of a res^3 grid on [0,1]^3, for a work-group
+// of 512 threads: thread t tests sub-point ((t%8 + 0.5)/8, ...) against the
+// balls, starting with the sample of the input-grid cell (resolution N) that
+// holds it.  Returns the count in thread 0.
+__device__ int count_cell(const double *__restrict__ p4, int64_t n, int N, int res, int64_t cell, double tol,
+                          int *red) {
     const int t = threadIdx.x;
     const int64_t cx = cell % res, cy = (cell / res) % res, cz = cell / ((int64_t)res * res);
     const double size = 1.0 / res;
@@ -45,11 +44,44 @@ __global__ __launch_bounds__(512) void covered_kernel(const double *__restrict__
     unsigned long long m = __ballot(cov);
     if ((t & 63) == 0) red[t >> 6] = __popcll(m);
     __syncthreads();
-    if (t == 0) {
-        int s = 0;
-        for (int w = 0; w < 8; ++w) s += red[w];
-        counts[cell] = s;
+    int sum = 0;
+    if (t == 0)
+        for (int w = 0; w < 8; ++w) sum += red[w];
+    return sum;
+}
+
+// One work-group per cell of one grid.
+__global__ __launch_bounds__(512) void covered_kernel(const double *__restrict__ p4, int64_t n, int N, int res,
+                                                      int64_t cell0, double tol, int *__restrict__ counts) {
+    __shared__ int red[8];
+    const int64_t cell = cell0 + blockIdx.x;
+    const int sum = count_cell(p4, n, N, res, cell, tol, red);
+    if (threadIdx.x == 0) counts[cell] = sum;
+}
+
+// Covered counts of many grids in one launch: job k owns global blocks
+// [start[k], start[k+1]) and counts the res_k^3 cells of the samples
+// p4 + 4 sample_off[k] (n_k samples on an N_k^3 grid) into out + out_off[k].
+struct CellJob {
+    int64_t sample_off, n, out_off;
+    int N, res;
+};
+
+__global__ __launch_bounds__(512) void covered_jobs_kernel(const double *__restrict__ p4_all, const CellJob *jobs,
+                                                           const int64_t *start, int njobs, int64_t block0,
+                                                           double tol, int *__restrict__ out) {
+    __shared__ int red[8];
+    const int64_t gb = block0 + blockIdx.x;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= gb) lo = mid;
+        else hi = mid - 1;
     }
+    const CellJob J = jobs[lo];
+    const int64_t cell = gb - start[lo];
+    const int sum = count_cell(p4_all + 4 * J.sample_off, J.n, J.N, J.res, cell, tol, red);
+    if (threadIdx.x == 0) out[J.out_off + cell] = sum;
 }
 
 sdfi_status counts_of(const double *p4, int64_t n, int N, int res, int *dev_counts, std::vector<int> &host,
@@ -100,14 +132,94 @@ std::vector<int64_t> flood(const std::vector<int> &cnt, int res) {
     return out;
 }
 
+// the children of the cells in flood order, each cell's 8 by ascending child
+// count (ties: child index bx + 2 by + 4 bz), as linear (2N)^3 indices
+void emit_children(const std::vector<int64_t> &cells, const int *child, int N, int64_t *out) {
+    const int64_t F = 2 * (int64_t)N;
+    int64_t k = 0;
+    for (int64_t c : cells) {
+        int64_t x = c % N, y = (c / N) % N, z = c / ((int64_t)N * N);
+        std::pair<int, int> kids[8];
+        int64_t qi[8];
+        for (int b = 0; b < 8; ++b) {
+            int64_t q = (2 * x + (b & 1)) + F * ((2 * y + ((b >> 1) & 1)) + F * (2 * z + ((b >> 2) & 1)));
+            kids[b] = {child[q], b};
+            qi[b] = q;
+        }
+        std::sort(kids, kids + 8);
+        for (int b = 0; b < 8; ++b) out[k++] = qi[kids[b].second];
+    }
+}
+
 }  // namespace
 
 size_t order_ws(int64_t n, int64_t m, const sdfi_options &o) {
-    // (2N)^3 cell counts; without a grid (batched instances) 8 n covers any
-    // instance of at most n samples
+    // (2N)^3 cell counts; without a grid (batched instances) the parent and
+    // child counts of every instance: 9 n
     int64_t fine = (int64_t)2 * o.grid;
-    int64_t cells = o.grid > 0 ? fine * fine * fine : 8 * n;
-    return sizeof(int) * (size_t)std::max<int64_t>(cells, 1) + 4096 + check_ws(0);
+    int64_t cells = o.grid > 0 ? fine * fine * fine : 9 * n;
+    return sizeof(int) * (size_t)std::max<int64_t>(cells, 1) + 4096 + check_ws(0) +
+           (o.grid > 0 ? 0 : (sizeof(CellJob) + sizeof(int64_t)) * (size_t)(2 * n + 4) + 1024);
+}
+
+// Refinement orders of many grid instances (instance b: samples rows
+// [soff[b], soff[b+1]) on a grids[b]^3 grid, queries its (2 grids[b])^3 child
+// cells): every covered count in one launch, one read-back, the flood fills
+// on the host, one upload.
+sdfi_status run_order_batched(int ninst, const int64_t *soff, const int32_t *grids, const double *samples,
+                              int64_t *order_out, Carver &ws, const sdfi_options &o, hipStream_t st) {
+    std::vector<CellJob> jobs;
+    std::vector<int64_t> start(1, 0);
+    int64_t outpos = 0;
+    for (int b = 0; b < ninst; ++b) {
+        const int N = grids[b];
+        for (int res : {N, 2 * N}) {
+            CellJob J;
+            J.sample_off = soff[b];
+            J.n = soff[b + 1] - soff[b];
+            J.out_off = outpos;
+            J.N = N;
+            J.res = res;
+            const int64_t cells = (int64_t)res * res * res;
+            jobs.push_back(J);
+            start.push_back(start.back() + cells);
+            outpos += cells;
+        }
+    }
+    const int njobs = (int)jobs.size();
+    int *dc = ws.take<int>(outpos > 0 ? outpos : 1);
+    CellJob *dj = ws.take<CellJob>(njobs);
+    int64_t *ds = ws.take<int64_t>(njobs + 1);
+    if (!ws.ok()) {
+        set_error("workspace too small for the refinement orders");
+        return SDFI_ERR_WORKSPACE;
+    }
+    SDFI_HIP(hipMemcpyAsync(dj, jobs.data(), sizeof(CellJob) * njobs, hipMemcpyHostToDevice, st));
+    SDFI_HIP(hipMemcpyAsync(ds, start.data(), sizeof(int64_t) * (njobs + 1), hipMemcpyHostToDevice, st));
+    for (int64_t b0 = 0; b0 < outpos; b0 += (int64_t(1) << 24)) {
+        const int64_t cnt = std::min<int64_t>(int64_t(1) << 24, outpos - b0);
+        covered_jobs_kernel<<<(unsigned)cnt, 512, 0, st>>>(samples, dj, ds, njobs, b0, o.tol, dc);
+        SDFI_HIP(hipGetLastError());
+    }
+    std::vector<int> host(outpos);
+    SDFI_HIP(hipMemcpyAsync(host.data(), dc, sizeof(int) * outpos, hipMemcpyDeviceToHost, st));
+    SDFI_HIP(hipStreamSynchronize(st));
+    std::vector<int64_t> order;
+    int64_t total = 0;
+    for (int b = 0; b < ninst; ++b) total += (int64_t)8 * grids[b] * grids[b] * grids[b];
+    order.resize(total);
+    int64_t qpos = 0;
+    for (int b = 0; b < ninst; ++b) {
+        const int N = grids[b];
+        std::vector<int> parent(host.begin() + jobs[2 * b].out_off,
+                                host.begin() + jobs[2 * b].out_off + (int64_t)N * N * N);
+        std::vector<int64_t> cells = flood(parent, N);
+        emit_children(cells, host.data() + jobs[2 * b + 1].out_off, N, order.data() + qpos);
+        qpos += (int64_t)8 * N * N * N;
+    }
+    SDFI_HIP(hipMemcpyAsync(order_out, order.data(), sizeof(int64_t) * total, hipMemcpyHostToDevice, st));
+    SDFI_HIP(hipStreamSynchronize(st));
+    return SDFI_OK;
 }
 
 sdfi_status run_order(const double *samples, int64_t n, const double *queries, int64_t m, int64_t *order_out,
@@ -127,19 +239,8 @@ sdfi_status run_order(const double *samples, int64_t n, const double *queries, i
     if (!queries) {
         s = counts_of(samples, n, N, 2 * N, dc, child, o, st);
         if (s != SDFI_OK) return s;
-        const int64_t F = 2 * N;
-        for (int64_t c : cells) {
-            int64_t x = c % N, y = (c / N) % N, z = c / ((int64_t)N * N);
-            std::pair<int, int> kids[8];
-            int64_t qi[8];
-            for (int b = 0; b < 8; ++b) {
-                int64_t q = (2 * x + (b & 1)) + F * ((2 * y + ((b >> 1) & 1)) + F * (2 * z + ((b >> 2) & 1)));
-                kids[b] = {child[q], b};
-                qi[b] = q;
-            }
-            std::sort(kids, kids + 8);
-            for (int b = 0; b < 8; ++b) order.push_back(qi[kids[b].second]);
-        }
+        order.resize(cells.size() * 8);
+        emit_children(cells, child.data(), N, order.data());
     } else {
         std::vector<double> hq(3 * m);
         SDFI_HIP(hipMemcpyAsync(hq.data(), queries, sizeof(double) * 3 * m, hipMemcpyDeviceToHost, st));

@@ -13,8 +13,7 @@
 
 namespace sdfi {
 
-sdfi_status run_witnesses(const double *samples, int64_t n, double *w, uint8_t *st, const sdfi_options &o,
-                          hipStream_t s);
+
 
 namespace {
 

@@ -184,6 +184,43 @@ def test_batched_equals_plain():
         assert torch.equal(b["order"][sl], p["order"])
 
 
+def test_batched_orders_and_witnesses_match_oracle():
+    # several instances: the one-launch covered counts and the segmented
+    # witness launch give each instance the oracle's refinement order, and the
+    # witnesses of its own samples only
+    inst = configs.batch(5, grids=(3, 4, 5))
+    tens = [(dev(np.c_[x.points, x.values]), dev(x.queries), x.grid) for x in inst]
+    print("batched orders", [x.grid for x in inst], flush=True)
+    b = sdfi.greedy_batched(tens, certify=True)
+    assert b["report"]["n_violations_pairwise"] == 0 and b["report"]["n_violations_witness"] == 0
+    qo = b["query_offsets"]
+    for i, x in enumerate(inst):
+        order, _, _ = OO.refinement_order(x.points, x.values, x.grid)
+        np.testing.assert_array_equal(b["order"][qo[i]:qo[i + 1]].cpu().numpy(), order)
+
+
+def test_batched_input_error_names_the_instance():
+    inst = configs.batch(3, grids=(3, 4))
+    tens = [(dev(np.c_[x.points, x.values]), dev(x.queries), x.grid) for x in inst]
+    bad = tens[2][0].clone()
+    bad[1, 3] = float("nan")
+    tens[2] = (bad, tens[2][1], tens[2][2])
+    with pytest.raises(RuntimeError, match="instance 2: .*NaN"):
+        sdfi.greedy_batched(tens)
+
+
+def test_many_instances_pick_either_block_size_with_identical_results():
+    # more instances than resident 512-thread groups: the default takes 4-wave
+    # groups, and the results equal those of the fixed 8-wave launch
+    inst = configs.batch(600, grids=(2, 3))
+    tens = [(dev(np.c_[x.points, x.values]), dev(x.queries), x.grid) for x in inst]
+    print("many instances", len(tens), flush=True)
+    a = sdfi.greedy_batched(tens, block_size=0)
+    b = sdfi.greedy_batched(tens, block_size=512)
+    for k in ("values", "kind", "active", "order"):
+        assert torch.equal(a[k], b[k]), k
+
+
 def test_batched_instance_matches_oracle():
     # a box on a coarse grid; a value depends only on earlier ones, so the
     # first 400 steps are compared (the oracle's later steps take minutes here)
