@@ -83,7 +83,11 @@ enum {
 /* option flags */
 enum {
     SDFI_OPT_CERTIFY = 1,      /* greedy/repair: run the Prop. 1 certificate on the result */
-    SDFI_OPT_INPUT_CHECK = 2   /* greedy: fail with SDFI_ERR_INVALID_INPUT if the samples violate Prop. 1 */
+    SDFI_OPT_INPUT_CHECK = 2,  /* greedy: fail with SDFI_ERR_INVALID_INPUT if the samples violate Prop. 1 */
+    SDFI_OPT_EXHAUSTIVE = 4    /* greedy: every exact sphere search that is not settled by its first
+                                  cover scan walks every rim against every cap (the search's
+                                  last resort) instead of growing a working cap subset; the
+                                  answers are the same, only slower.  For testing that path. */
 };
 
 typedef struct {

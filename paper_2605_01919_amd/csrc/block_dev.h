@@ -24,6 +24,10 @@ enum {
     // run; searches that reach the exhaustive walk; wave ticks in the first
     // cover scan and in the rounds
     RP_LN_EARLY, RP_LN_FIRST, RP_LN_LOOP, RP_LN_ROUNDS, RP_LN_FALLBACK, RP_LN_T_FIRST, RP_LN_T_LOOP,
+    // wave ticks in the exhaustive walks and the caps they walked; rounds that
+    // ended because the covering cap was already in the subset; passes run
+    // with the widened bound and with no bound
+    RP_LN_T_FALLBACK, RP_LN_FALLBACK_CAPS, RP_LN_STALLED, RP_PASS_WIDE, RP_PASS_OPEN,
     RP_COUNT
 };
 
@@ -256,7 +260,7 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
                                  double tie, int64_t *list, Cap (*kp)[geom::KMAX], int64_t (*kid)[geom::KMAX],
                                  int32_t *flist, int fcap,
                                  Shared<NW> &S, double *r_out, double *x_out, int64_t *sphere_out,
-                                 unsigned long long *prof = nullptr) {
+                                 unsigned long long *prof = nullptr, int walk_only = 0) {
     const int tid = threadIdx.x;
     const int BS = NW * 64;
     unsigned long long tmark = (prof && tid == 0) ? wall_clock64() : 0ull;
@@ -346,6 +350,8 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
         lap(RP_T_LIST);
         if (prof && tid == 0) {
             prof[RP_PASSES] += 1;
+            if (pass == 1) prof[isinf(bound) ? RP_PASS_OPEN : RP_PASS_WIDE] += 1;
+            if (pass == 2) prof[RP_PASS_OPEN] += 1;
             prof[RP_LIST_LEN] += (unsigned long long)len;
             prof[RP_LOCAL_LEN] += (unsigned long long)nl;
         }
@@ -361,6 +367,7 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
         L.lq[2] = q[2];
         L.lb = INFINITY;  // already applied by the index list
         L.use_region = 0;
+        L.walk_only = walk_only;
         if (tid == 0) {
             S.counter = 0;
             S.bound_bits = __double_as_longlong(bound);

@@ -36,7 +36,6 @@ namespace sdfi {
 namespace geom {
 
 constexpr int KMAX = 128;            // working cap subset per wavefront
-constexpr double ARC_EPS = 1e-12;    // points with C.P - cos beta up to this count as uncovered
 constexpr double NUDGE = 1e-7;       // witnesses move this far (rad) off the rim they sit on
 constexpr double COVER_EPS = 1e-13;  // cover margins v.u - c up to this count as uncovered (rounding)
 constexpr int FALLBACK_LDS = 512;     // cap list of the exhaustive search held in LDS
@@ -69,6 +68,9 @@ struct Balls {
     // every question asked about points of the region.
     int use_region = 0;
     double ru[3] = {0.0, 0.0, 0.0}, rc = -1.0, rs = 0.0;
+    // searches over these balls skip the subset rounds and go straight to
+    // the exhaustive rim walk (testing that path)
+    int walk_only = 0;
 };
 
 __device__ inline double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
@@ -157,6 +159,7 @@ __device__ inline void rim_dir(const Rim &R, double px, double py, double *v) {
 struct Arc {
     double cx, cy;  // centre direction
     double k, s;    // cos and sin of the half-width
+    double amp;     // |(A, B)|: the cover margin v.u_f - c_f at P is amp (C.P - k)
 };
 
 // arc of cap f on rim R: returns 0 none, 1 arc, 2 whole rim
@@ -170,10 +173,15 @@ __device__ inline int arc_of(const Rim &R, const Cap &f, Arc &a) {
     a.cy = Bc / amp;
     a.k = fmin(1.0, fmax(-1.0, K / amp));
     a.s = sqrt(fmax(0.0, 1.0 - a.k * a.k));
+    a.amp = amp;
     return 1;
 }
 
-__device__ inline bool arc_covers(const Arc &a, double px, double py) { return a.cx * px + a.cy * py - a.k > ARC_EPS; }
+// the same test as the cover scans (margin v.u_f - c_f > COVER_EPS), so that a
+// point the walk leaves uncovered is not found covered by a cap of the walk
+__device__ inline bool arc_covers(const Arc &a, double px, double py) {
+    return a.amp * (a.cx * px + a.cy * py - a.k) > COVER_EPS;
+}
 
 // dir > 0: the end met walking forward (C rotated by +beta); dir < 0: the start
 __device__ inline void arc_end(const Arc &a, int dir, double &ex, double &ey) {
@@ -545,7 +553,7 @@ __device__ inline int lazy_exist(const Balls &B0, const double *o, double r, con
     }
     k = 1;
     wave_sync_lds();
-    for (int round = 0; round < 4 * KMAX; ++round) {
+    for (int round = 0; round < (B.walk_only ? 0 : 4 * KMAX); ++round) {
         // 1. uncovered gap midpoints w.r.t. the working subset: each lane walks
         //    rims lane and lane + 64 of the subset and keeps the first hit
         const SubsetCaps sub{kp, k};
@@ -676,7 +684,9 @@ constexpr int NHOLD = 32;
 struct Holders {
     int64_t *h;  // NHOLD entries (LDS)
     int *next;   // ring position (LDS)
-    unsigned long long *prof = nullptr;  // optional search profile: early, first, loop, rounds, fallback, ticks
+    // optional search profile: early, first, loop, rounds, fallback, first
+    // ticks, loop ticks, fallback ticks, fallback caps, stalled rounds
+    unsigned long long *prof = nullptr;
     __device__ void note(int k, unsigned long long v) {
         if (prof && (threadIdx.x & 63) == 0) atomicAdd(&prof[k], v);
     }
@@ -784,7 +794,7 @@ __device__ __noinline__ int lazy_nearest(const Balls &B0, const double *o, doubl
     }
     wave_sync_lds();
     double lowest = d0;  // every uncovered point is at least this far from q
-    for (int round = 0; round < 8 * KMAX; ++round) {
+    for (int round = 0; round < (B.walk_only ? 0 : 8 * KMAX); ++round) {
         if (hold) hold->note(3, 1);
         const SubsetCaps sub{kp, k};
         double cd = INFINITY, cpx = 0.0, cpy = 0.0;
@@ -865,6 +875,7 @@ __device__ __noinline__ int lazy_nearest(const Balls &B0, const double *o, doubl
         }
         bool have = false;
         for (int e = 0; e < k; ++e) have |= (kid[e] == arg);
+        if (have && hold) hold->note(9, 1);
         if (have || k >= KMAX) break;
         if (lane == 0) {
             kid[k] = arg;
@@ -877,7 +888,15 @@ __device__ __noinline__ int lazy_nearest(const Balls &B0, const double *o, doubl
     // lazy_exist).  When capped, return -1 with the last subset-nearest
     // distance, a lower bound.
     if (hold) hold->note(4, 1);
+    struct FallbackTicks {
+        Holders *h;
+        unsigned long long t;
+        __device__ ~FallbackTicks() {
+            if (h) h->note(7, wall_clock64() - t);
+        }
+    } fallback_ticks{hold, (hold && hold->prof) ? wall_clock64() : 0ull};
     const int ncap = wave_list_caps(B, o, r, cl, ccap);
+    if (hold) hold->note(8, (unsigned long long)ncap);
     if (ncap > ccap) {
         *dist_out = lowest;
         return -1;

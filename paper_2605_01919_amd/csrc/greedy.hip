@@ -70,6 +70,7 @@ struct GInst {
     unsigned long long *counts;  // C_NCOUNT
     int64_t n, m;
     int profile;             // record the finer sub-phase split (while timing is enabled)
+    int walk_only;           // exact searches take the exhaustive rim walk (SDFI_OPT_EXHAUSTIVE)
 };
 
 template <int NW>
@@ -157,6 +158,7 @@ __device__ void revalidate(const GInst &I, int64_t N, const double *q, double s,
         B.lb = INFINITY;
         B.idx = nullptr;
         B.use_region = 0;
+        B.walk_only = I.walk_only;
         for (int64_t guard = 0; guard <= nthr; ++guard) {
             int t = 0;
             if (ln == 0) t = atomicAdd(&SH.counter, 1);
@@ -303,7 +305,8 @@ __global__ __launch_bounds__(NW * 64) void greedy_kernel(const GInst *insts, dou
                             B.skip = -1;
                             B.lb = INFINITY;
                             B.idx = nullptr;
-        B.use_region = 0;
+                            B.use_region = 0;
+                            B.walk_only = I.walk_only;
                             double x[3];
                             int st = geom::lazy_exist_call(B, q, r, cw[e], SH.kp[0], SH.kid[0], I.flist, I.fcap, x,
                                                            &I.counts[C_WALKS]);
@@ -360,7 +363,8 @@ __global__ __launch_bounds__(NW * 64) void greedy_kernel(const GInst *insts, dou
                         double rr, x[3];
                         int64_t sph;
                         int kk = blk::rmin_block<NW>(q, sigma, I.CP, I.CW, N, tol, tie, I.list, SH.kp, SH.kid, I.flist,
-                                                     I.fcap, SH.S, &rr, x, &sph, I.profile ? I.counts + C_RP0 : nullptr);
+                                                     I.fcap, SH.S, &rr, x, &sph, I.profile ? I.counts + C_RP0 : nullptr,
+                                                     I.walk_only);
                         if (kk == -2 && tid == 0) atomicAdd(&I.counts[C_NUMERIC], 1ull);
                         if (kk > 0) {
                             val = sigma * rr;
@@ -749,6 +753,7 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
         fpos += (int64_t)nw * g.fcap;
         g.counts = b.counts + C_NCOUNT * i;
         g.profile = timing_enabled() ? 1 : 0;
+        g.walk_only = (o.flags & SDFI_OPT_EXHAUSTIVE) ? 1 : 0;
         g.n = ni;
         g.m = mi;
         cpos += ni + mi;
@@ -802,7 +807,8 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
             "greedy_cover_ticks", "greedy_vnew_ticks", "greedy_threat_ticks", "greedy_reval_ticks",
             "greedy_threatened", "rmin_scan_ticks", "rmin_ray_ticks", "rmin_list_ticks", "rmin_search_ticks",
             "rmin_calls", "rmin_passes", "rmin_list_len", "rmin_local_len", "rmin_searches", "ln_early", "ln_first",
-            "ln_loop", "ln_rounds", "ln_fallback", "ln_first_ticks", "ln_loop_ticks"};
+            "ln_loop", "ln_rounds", "ln_fallback", "ln_first_ticks", "ln_loop_ticks", "ln_fallback_ticks",
+            "ln_fallback_caps", "ln_stalled", "rmin_wide_passes", "rmin_open_passes"};
         for (int k = C_T_COVER; k < C_NCOUNT; ++k) {
             unsigned long long tot = 0;
             for (int i = 0; i < ninst; ++i) tot += cnt[C_NCOUNT * i + k];

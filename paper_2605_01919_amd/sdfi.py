@@ -26,6 +26,7 @@ KIND_INFEASIBLE, KIND_UNRESOLVED = 254, 255
 
 OPT_CERTIFY = 1
 OPT_INPUT_CHECK = 2
+OPT_EXHAUSTIVE = 4
 
 
 class Options(ctypes.Structure):
@@ -229,12 +230,14 @@ def sample_witnesses(samples):
 
 
 def greedy(samples, queries, order=None, grid=0, certify=False, input_check=False, sample_witness=False,
-           block_size=0):
-    """Greedy interpolation.  Returns a dict of GPU tensors and the host report."""
+           block_size=0, exhaustive=False):
+    """Greedy interpolation.  Returns a dict of GPU tensors and the host report.
+    exhaustive: the exact searches take their last-resort rim walk (testing)."""
     samples = _dev(samples, torch.float64, 4, "samples")
     queries = _dev(queries, torch.float64, 3, "queries")
     n, m = samples.shape[0], queries.shape[0]
     flags = (OPT_CERTIFY if certify else 0) | (OPT_INPUT_CHECK if input_check else 0)
+    flags |= OPT_EXHAUSTIVE if exhaustive else 0
     opt = options(grid=grid, flags=flags, block_size=block_size)
     dev = samples.device
     if order is not None:

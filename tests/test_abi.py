@@ -86,6 +86,12 @@ def test_counters_and_block_size_on_host():
     o = sdfi.options(block_size=1024)
     assert L.sdfi_workspace_size(4, 5000, 40000, ctypes.byref(o), ctypes.byref(size)) == 1
     assert b"block_size" in L.sdfi_last_error()
+    # the documented flags pass, any other bit is refused
+    o = sdfi.options(flags=sdfi.OPT_CERTIFY | sdfi.OPT_INPUT_CHECK | sdfi.OPT_EXHAUSTIVE)
+    assert L.sdfi_workspace_size(4, 5000, 40000, ctypes.byref(o), ctypes.byref(size)) == 0
+    o = sdfi.options(flags=8)
+    assert L.sdfi_workspace_size(4, 5000, 40000, ctypes.byref(o), ctypes.byref(size)) == 1
+    assert b"flags" in L.sdfi_last_error()
 
 
 def test_noalloc_rejects_sizes_beyond_its_scratch():

@@ -155,22 +155,32 @@ def test_backward_with_minimum_radius_parents():
 
 
 def test_rare_search_paths_match_oracle():
-    """A 5^3 box instance whose minimum-radius searches take the exhaustive
-    rim walk (the working cap subset exhausted) and the second, wider pass:
-    device counters show both, and every one of its 1000 steps is replayed."""
+    """A 5^3 box instance whose minimum-radius searches take the second,
+    wider pass, run once as is and once with every refined search forced onto
+    the exhaustive rim walk (the searches' last resort): device counters show
+    both paths, and every one of the 1000 steps of each run is replayed."""
     x = configs.batch_instance(4, grids=(5,))
     s, q = dev(np.c_[x.points, x.values]), dev(x.queries)
-    sdfi.timing(True)
-    g = sdfi.greedy(s, q, grid=x.grid, certify=True, sample_witness=True)
-    walks = sdfi.counter_read("ln_fallback")
-    passes, calls = sdfi.counter_read("rmin_passes"), sdfi.counter_read("rmin_calls")
-    sdfi.timing(False)
-    print("exhaustive walks", walks, "second passes", passes - calls, flush=True)
-    assert walks > 0 and passes > calls
+    runs = {}
+    for exhaustive in (False, True):
+        sdfi.timing(True)
+        g = sdfi.greedy(s, q, grid=x.grid, certify=True, sample_witness=True, exhaustive=exhaustive)
+        walks = sdfi.counter_read("ln_fallback")
+        passes, calls = sdfi.counter_read("rmin_passes"), sdfi.counter_read("rmin_calls")
+        sdfi.timing(False)
+        print("exhaustive", exhaustive, "walks", walks, "second passes", passes - calls, flush=True)
+        assert passes > calls
+        assert (walks > 0) == exhaustive
+        rep = g["report"]
+        assert rep["n_violations_pairwise"] == 0 and rep["n_violations_witness"] == 0, rep
+        runs[exhaustive] = g
     # the profile changes nothing
     g2 = sdfi.greedy(s, q, grid=x.grid)
-    assert torch.equal(torch.nan_to_num(g["values"], nan=7.0), torch.nan_to_num(g2["values"], nan=7.0))
-    rep = g["report"]
-    assert rep["n_violations_pairwise"] == 0 and rep["n_violations_witness"] == 0, rep
-    r = replay(x.points, x.values, x.queries, g, np.arange(x.m))
-    assert_replay_matches(g, r, x.n)
+    assert torch.equal(torch.nan_to_num(runs[False]["values"], nan=7.0), torch.nan_to_num(g2["values"], nan=7.0))
+    # both search paths give the same kinds and values up to rounding
+    a, b = runs[False], runs[True]
+    assert torch.equal(a["kind"], b["kind"]) and torch.equal(a["order"], b["order"])
+    assert torch.allclose(a["values"], b["values"], rtol=0, atol=1e-9, equal_nan=True)
+    for g in (a, b):
+        r = replay(x.points, x.values, x.queries, g, np.arange(x.m))
+        assert_replay_matches(g, r, x.n)
