@@ -25,9 +25,14 @@ enum {
     // cover scan and in the rounds
     RP_LN_EARLY, RP_LN_FIRST, RP_LN_LOOP, RP_LN_ROUNDS, RP_LN_FALLBACK, RP_LN_T_FIRST, RP_LN_T_LOOP,
     // wave ticks in the exhaustive walks and the caps they walked; rounds that
-    // ended because the covering cap was already in the subset; passes run
-    // with the widened bound and with no bound
-    RP_LN_T_FALLBACK, RP_LN_FALLBACK_CAPS, RP_LN_STALLED, RP_PASS_WIDE, RP_PASS_OPEN,
+    // ended because the covering cap was already in the subset; wave ticks in
+    // the searches that ended early (holder or bound)
+    RP_LN_T_FALLBACK, RP_LN_FALLBACK_CAPS, RP_LN_STALLED, RP_LN_T_EARLY,
+    // passes run with the widened bound and with no bound; candidates that
+    // the recent holders settled before any search; wave ticks in the
+    // candidate pulls as a whole (searches included, waits at the end of the
+    // pass excluded)
+    RP_PASS_WIDE, RP_PASS_OPEN, RP_PRE_HELD, RP_T_PULL,
     RP_COUNT
 };
 
@@ -386,6 +391,7 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
         // lower bounds together, then the survivors are searched in list order
         // (re-pruned against the bound as it shrinks)
         constexpr int PULL = 16;
+        const unsigned long long t_pull = prof ? wall_clock64() : 0ull;
         for (int guard = 0; guard < (1 << 30); ++guard) {
             int k0 = 0;
             if (lane() == 0) k0 = atomicAdd(&S.counter, PULL);
@@ -401,6 +407,33 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
                 myprune = myi == deepest ? mylb : dist_outside_ball(q, pp, fabs(pp[3]), pdeep, Rdeep);
             }
             unsigned long long pending = __ballot(have);
+            {
+                // the recent holders first, for the PULL candidates together:
+                // lane l tests candidate l % PULL against a quarter of the ring
+                // (a holder proves that the sphere has no uncovered point within
+                // the bound; the bound only shrinks afterwards)
+                static_assert(PULL == 16 && geom::NHOLD % 4 == 0, "four holder groups per candidate");
+                unsigned long long cb = 0;
+                if (lane() == 0) cb = __hip_atomic_load(&S.bound_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                const double cur = __longlong_as_double((long long)__shfl(cb, 0, 64));
+                const int cj = lane() & (PULL - 1), hg = lane() / PULL;
+                const int64_t ci = __shfl(myi, cj, 64);
+                int hit = 0;
+                if ((pending >> cj) & 1ull) {
+                    const double *pc = p4 + 4 * ci;
+                    const double oc[3] = {pc[0], pc[1], pc[2]};
+                    const double rc = fabs(pc[3]);
+                    Balls Rg = L;
+                    if (!geom::set_region(Rg, oc, rc, q, cur * (1.0 + 1e-12) + 1e-15))
+                        hit = 1;
+                    else
+                        hit = geom::held_by(Rg, oc, rc, S.hball + hg * (geom::NHOLD / 4), geom::NHOLD / 4);
+                }
+                const unsigned long long hb = __ballot(hit);
+                const unsigned long long held = (hb | (hb >> 16) | (hb >> 32) | (hb >> 48)) & 0xFFFFull;
+                if (prof && lane() == 0 && (pending & held)) atomicAdd(&prof[RP_PRE_HELD], (unsigned long long)__popcll(pending & held));
+                pending &= ~held;
+            }
             while (pending) {
                 unsigned long long cb = 0;
                 if (lane() == 0) cb = __hip_atomic_load(&S.bound_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -438,6 +471,7 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
                 }
             }
         }
+        if (prof && lane() == 0) atomicAdd(&prof[RP_T_PULL], wall_clock64() - t_pull);
         if (lane() == 0) {
             S.wlow[w] = wlow;
             S.wd[w] = wd;

@@ -676,6 +676,44 @@ __device__ __noinline__ int lazy_exist_call(const Balls &B, const double *o, dou
     return lazy_exist(B, o, r, hint, kp, kid, cl, ccap, x, walks);
 }
 
+// The region of interest of a nearest search: the points of sphere (o, r)
+// within `bound` of q, the cap {v : v.g/|g| >= rc} with g = q - o.  Returns
+// 0 when no point of the sphere is that close; else 1, with B's region set
+// (use_region 0 when the region is the whole sphere).
+__device__ inline int set_region(Balls &B, const double *o, double r, const double *q, double bound) {
+    const double g[3] = {q[0] - o[0], q[1] - o[1], q[2] - o[2]};
+    const double gn = sqrt(dot3(g, g));
+    B.use_region = 0;
+    if (bound < INFINITY && gn > 0.0) {
+        const double rc = (r * r + gn * gn - bound * bound) / (2.0 * r * gn);
+        if (rc > 1.0) return 0;
+        if (rc > -1.0) {
+            B.use_region = 1;
+            B.ru[0] = g[0] / gn;
+            B.ru[1] = g[1] / gn;
+            B.ru[2] = g[2] / gn;
+            B.rc = rc;
+            B.rs = sqrt(fmax(0.0, 1.0 - rc * rc));
+        }
+    }
+    if (gn > 0.0 && fabs(gn - r) > bound) return 0;  // the nearest point of the sphere is farther
+    return 1;
+}
+
+// Does one of the balls ring[0..nh) (indices of B, -1 empty, read as they
+// stand) hold every point of B's region?  Exact for each ball read.
+__device__ inline bool held_by(const Balls &B, const double *o, double r, const int64_t *ring, int nh) {
+    if (!B.use_region) return false;
+    for (int j = 0; j < nh; ++j) {
+        const int64_t f = __hip_atomic_load(&ring[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (f < 0 || f >= ball_count(B)) continue;
+        Cap ch;
+        const int st = cap_of(B, f, o, r, ch);
+        if (st == 2 || (st == 1 && region_held(B, ch))) return true;
+    }
+    return false;
+}
+
 // Recently seen balls that held a whole search region (ball indices, -1
 // empty): a ring of NHOLD entries in LDS shared by the wavefronts of a
 // work-group.  Entries may be replaced while another wave reads them; any
@@ -685,7 +723,8 @@ struct Holders {
     int64_t *h;  // NHOLD entries (LDS)
     int *next;   // ring position (LDS)
     // optional search profile: early, first, loop, rounds, fallback, first
-    // ticks, loop ticks, fallback ticks, fallback caps, stalled rounds
+    // ticks, loop ticks, fallback ticks, fallback caps, stalled rounds, early
+    // ticks
     unsigned long long *prof = nullptr;
     __device__ void note(int k, unsigned long long v) {
         if (prof && (threadIdx.x & 63) == 0) atomicAdd(&prof[k], v);
@@ -706,22 +745,15 @@ __device__ __noinline__ int lazy_nearest(const Balls &B0, const double *o, doubl
                                    int64_t *kid, int32_t *cl, int ccap, double *dist_out, double *x,
                                    Holders *hold = nullptr) {
     const int lane = threadIdx.x & 63;
+    const unsigned long long t_enter = (hold && hold->prof) ? wall_clock64() : 0ull;
     double g[3] = {q[0] - o[0], q[1] - o[1], q[2] - o[2]};
     double gn = sqrt(dot3(g, g));
     // only points of the sphere within `bound` of q matter: the cap v.g/|g| >= rc
     Balls B = B0;
-    B.use_region = 0;
-    if (bound < INFINITY && gn > 0.0) {
-        double rc = (r * r + gn * gn - bound * bound) / (2.0 * r * gn);
-        if (rc > 1.0) return 0;  // no point of the sphere is that close
-        if (rc > -1.0) {
-            B.use_region = 1;
-            B.ru[0] = g[0] / gn;
-            B.ru[1] = g[1] / gn;
-            B.ru[2] = g[2] / gn;
-            B.rc = rc;
-            B.rs = sqrt(fmax(0.0, 1.0 - rc * rc));
-        }
+    if (!set_region(B, o, r, q, bound) && gn > 0.0) {
+        if (hold) hold->note(0, 1);
+        if (hold) hold->note(10, wall_clock64() - t_enter);
+        return 0;  // no point of the sphere is that close
     }
     double mx;
     int64_t arg;
@@ -739,27 +771,15 @@ __device__ __noinline__ int lazy_nearest(const Balls &B0, const double *o, doubl
     }
     double v0[3] = {g[0] / gn, g[1] / gn, g[2] / gn};
     double d0 = fabs(gn - r);
-    if (d0 > bound) {
-        if (hold) hold->note(0, 1);
-        return 0;
-    }
     // a single ball holding every point of the sphere within the bound ends
     // the search; the balls that did so recently (ball indices of B0) are
     // tried on their own first
     int held = 0;
     if (hold && B.use_region) {
         // one recent holder per lane
-        int hit = 0;
-        if (lane < NHOLD) {
-            const int64_t f = __hip_atomic_load(&hold->h[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (f >= 0 && f < ball_count(B)) {
-                Cap ch;
-                const int st = cap_of(B, f, o, r, ch);
-                hit = st == 2 || (st == 1 && region_held(B, ch));
-            }
-        }
-        if (wor(hit)) {
+        if (wor(lane < NHOLD && held_by(B, o, r, hold->h + lane, 1))) {
             hold->note(0, 1);
+            hold->note(10, wall_clock64() - t_enter);
             return 0;
         }
     }

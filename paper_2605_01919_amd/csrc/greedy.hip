@@ -808,7 +808,8 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
             "greedy_threatened", "rmin_scan_ticks", "rmin_ray_ticks", "rmin_list_ticks", "rmin_search_ticks",
             "rmin_calls", "rmin_passes", "rmin_list_len", "rmin_local_len", "rmin_searches", "ln_early", "ln_first",
             "ln_loop", "ln_rounds", "ln_fallback", "ln_first_ticks", "ln_loop_ticks", "ln_fallback_ticks",
-            "ln_fallback_caps", "ln_stalled", "rmin_wide_passes", "rmin_open_passes"};
+            "ln_fallback_caps", "ln_stalled", "ln_early_ticks", "rmin_wide_passes", "rmin_open_passes",
+            "rmin_pre_held", "rmin_pull_ticks"};
         for (int k = C_T_COVER; k < C_NCOUNT; ++k) {
             unsigned long long tot = 0;
             for (int i = 0; i < ninst; ++i) tot += cnt[C_NCOUNT * i + k];
