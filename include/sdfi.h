@@ -104,6 +104,11 @@ typedef struct {
                               batched launch has more instances than resident
                               512-thread work-groups */
     uint32_t flags;        /* SDFI_OPT_* */
+    int32_t groups;        /* work-groups that share one instance of sdfi_greedy_interpolate
+                              (its minimum-radius and re-validation searches are spread
+                              over them; a cooperative launch), 0 = 16; capped at the
+                              groups the device keeps resident; 1 = one group.  Batched
+                              launches run one group per instance. */
 } sdfi_options;
 
 typedef struct {

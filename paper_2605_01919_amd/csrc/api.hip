@@ -131,6 +131,10 @@ sdfi_status read_options(const sdfi_options *opt, sdfi_options *out) {
         set_error("block_size must be 0, 256 or 512, got %d", out->block_size);
         return SDFI_ERR_INVALID_ARGUMENT;
     }
+    if (out->groups < 0 || out->groups > 1024) {
+        set_error("groups must be in [0, 1024], got %d", out->groups);
+        return SDFI_ERR_INVALID_ARGUMENT;
+    }
     if (out->flags & ~(uint32_t)(SDFI_OPT_CERTIFY | SDFI_OPT_INPUT_CHECK | SDFI_OPT_EXHAUSTIVE)) {
         set_error("unknown option flags 0x%x", out->flags);
         return SDFI_ERR_INVALID_ARGUMENT;

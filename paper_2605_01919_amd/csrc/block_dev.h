@@ -2,6 +2,8 @@
 // minimum valid radius used by the greedy fallback and by the repair.
 #pragma once
 
+#include <hip/hip_cooperative_groups.h>
+
 #include "geom_dev.h"
 
 namespace sdfi {
@@ -54,9 +56,153 @@ struct Shared {
     double wlow[NW];
     int64_t hball[geom::NHOLD];  // balls that held whole search regions (this pass's local numbering)
     int hnext;
+    // group_exist: each wave's part of the first cover test, and the result
+    double gmx[NW];
+    int64_t garg[NW], gpos[NW];
+    int gwhole[NW], gcnt[NW], gecap[NW];
+    int gst;
+    double gx[3];
 };
 
+// Several work-groups on one instance (a cooperative launch): group 0 runs
+// the greedy and posts the steps whose work is many independent sphere
+// searches (the minimum-radius candidate pulls, the re-validations) as jobs
+// on a board in global memory; every group takes items of a job from the
+// shared counter.  Grid-wide barriers open and close each job.
+enum { J_RMIN = 1, J_REVAL = 2, J_EXIT = 3 };
+
+struct Job {
+    int type;
+    int counter;                    // next item: candidate (pull at a time) or threatened sphere
+    int fail;                       // re-validation: a sphere has no uncovered point left
+    int keep_going;                 // re-validation: search every sphere even after a failure
+    unsigned long long bound_bits;  // minimum radius: best distance so far (bits of a double >= 0)
+    double q[3];
+    double s;                       // re-validation: value of the new ball
+    double Rdeep, tie;
+    int64_t N, len, nl, deepest, nthr;
+    // the holder ring of the minimum-radius searches, shared by the team
+    int64_t hring[geom::NHOLD];
+    int hnext;
+};
+
+// one group's best minimum-radius answer of a pass
+struct GroupBest {
+    double d, lb, low, x[3];
+    int64_t i;
+    int kind, nd;
+};
+
+struct Team {
+    Job *job;
+    GroupBest *best;  // one slot per group
+    int groups;
+};
+
+__device__ inline void team_sync() { cooperative_groups::this_grid().sync(); }
+
 __device__ inline int wid() { return threadIdx.x >> 6; }
+
+// geom::lazy_exist for a whole work-group: the waves split the first cover
+// test (which also lists the balls that meet the sphere) over slices of the
+// balls, the slices' lists are joined in ball order, and wave 0 goes on
+// alone, exactly as lazy_exist would.  cl: NW lists of ccap entries (one per
+// wave; wave 0's receives the joined list).  Every thread gets the status
+// and the point.
+template <int NW>
+__device__ __noinline__ int group_exist(const Balls &B, const double *o, double r, const double *hint, Cap *kp, int64_t *kid,
+                           int32_t *cl, int ccap, double *x, unsigned long long *walks, Shared<NW> &S) {
+    const int w = threadIdx.x >> 6;
+    if (!(r > 0.0)) {
+        // a point sphere: one wave's test
+        if (w == 0) {
+            const int st = geom::lazy_exist(B, o, r, hint, kp, kid, cl, ccap, x, walks);
+            if ((threadIdx.x & 63) == 0) {
+                S.gst = st;
+                S.gx[0] = x[0];
+                S.gx[1] = x[1];
+                S.gx[2] = x[2];
+            }
+        }
+        __syncthreads();
+        const int st = S.gst;
+        x[0] = S.gx[0];
+        x[1] = S.gx[1];
+        x[2] = S.gx[2];
+        __syncthreads();
+        return st;
+    }
+    double vh[3] = {1.0, 0.0, 0.0};
+    if (hint) {
+        double g[3] = {hint[0] - o[0], hint[1] - o[1], hint[2] - o[2]};
+        double gn = sqrt(geom::dot3(g, g));
+        if (gn > 0.0) {
+            vh[0] = g[0] / gn;
+            vh[1] = g[1] / gn;
+            vh[2] = g[2] / gn;
+        }
+    }
+    const int64_t n = geom::ball_count(B);
+    const int64_t chunk = ((n + NW - 1) / NW + 63) / 64 * 64;
+    const int64_t fb = min(n, (int64_t)w * chunk), fe = min(n, fb + chunk);
+    double mx;
+    int64_t arg, pos;
+    int whole, cnt, ecap;
+    geom::wave_cover_list(B, o, r, vh, &mx, &arg, &whole, cl + (int64_t)w * ccap, ccap, &cnt, &ecap, &pos, fb, fe);
+    if ((threadIdx.x & 63) == 0) {
+        S.gmx[w] = mx;
+        S.garg[w] = arg;
+        S.gpos[w] = pos;
+        S.gwhole[w] = whole;
+        S.gcnt[w] = cnt;
+        S.gecap[w] = ecap;
+    }
+    __syncthreads();
+    // join: the largest margin (lowest ball index among equals: the first such
+    // slice), the list in ball order, its position there
+    int total = 0, fits = 1, bw = 0, off_bw = 0, off_w = 0;
+    whole = 0;
+    ecap = 0;
+    mx = -INFINITY;
+    for (int v = 0; v < NW; ++v) {
+        if (v == w) off_w = total;
+        whole |= S.gwhole[v];
+        ecap |= S.gecap[v];
+        fits &= S.gcnt[v] <= ccap;
+        if (S.gmx[v] > mx) {
+            mx = S.gmx[v];
+            bw = v;
+            off_bw = total;
+        }
+        total += S.gcnt[v];
+    }
+    fits &= total <= ccap;
+    arg = S.garg[bw];
+    pos = arg >= B.N ? (int64_t)total : off_bw + S.gpos[bw];  // the extra ball sits after the rows
+    if (fits && w > 0) {
+        const int c = S.gcnt[w];
+        for (int k = threadIdx.x & 63; k < c; k += 64) cl[off_w + k] = cl[(int64_t)w * ccap + k];
+    }
+    __threadfence_block();
+    __syncthreads();
+    if (w == 0) {
+        const int st = geom::lazy_exist_rest(B, o, r, vh, kp, kid, cl, ccap, x, walks, mx, arg, whole,
+                                             fits ? total : ccap + 1, ecap, pos);
+        if ((threadIdx.x & 63) == 0) {
+            S.gst = st;
+            S.gx[0] = x[0];
+            S.gx[1] = x[1];
+            S.gx[2] = x[2];
+        }
+    }
+    __syncthreads();
+    const int st = S.gst;
+    x[0] = S.gx[0];
+    x[1] = S.gx[1];
+    x[2] = S.gx[2];
+    __syncthreads();
+    return st;
+}
 __device__ inline int lane() { return threadIdx.x & 63; }
 
 template <int NW>
@@ -260,12 +406,218 @@ __device__ __noinline__ double ray_bound(const double *q, int sigma, const doubl
 // d < |s| - tol.  Returns kind 0 (q in no sigma ball: radius 0),
 // 1 T, 2 D, 3 U, -1 nothing found, -2 a search hit its cap (no answer).  list: scratch of 2 (N + 1) entries;
 // kp/kid: per wave LDS scratch; flist: NW lists of fcap entries (global) for exhaustive searches.
+// candidates a wave of a team takes at a time (a group alone takes 16)
+constexpr int TEAM_PULL = 2;
+
+// The candidate pulls of one minimum-radius pass, for every wave of the
+// calling work-group: candidates list[0..len) (ball rows of p4, list[0] the
+// deepest ball), local set lset[0..nl) (the balls that can cover a point
+// within the pass bound of q), shared pull counter and best-distance bits
+// (LDS for one group, the job board for a team).  Each wave's best ends in
+// S.wd/wnd/wlb/wi/wk/wx/wlow[w].  ring/ring_next: the holder ring (null:
+// this group's own, cleared here; else a team's, cleared by the poster).
 template <int NW>
-__device__ inline int rmin_block(const double *q, int sigma, const double *p4, const double *W, int64_t N, double tol,
+__device__ __noinline__ void rmin_pull(const double *q, const double *p4, double tie, const int64_t *list, int64_t len,
+                          const int64_t *lset, int64_t nl, int64_t deepest, double Rdeep, int *counter,
+                          unsigned long long *bound_bits, Cap (*kp)[geom::KMAX], int64_t (*kid)[geom::KMAX],
+                          int32_t *flist, int fcap, Shared<NW> &S, unsigned long long *prof, int walk_only,
+                          int64_t *ring = nullptr, int *ring_next = nullptr) {
+    const double *pdeep = p4 + 4 * deepest;
+    Balls L;
+    L.p4 = p4;
+    L.N = nl;
+    L.idx = lset;
+    L.has_extra = 0;
+    L.tol = tie;  // contour of the balls shrunk by the uniqueness tolerance only
+    L.skip = -1;
+    L.lq[0] = q[0];
+    L.lq[1] = q[1];
+    L.lq[2] = q[2];
+    L.lb = INFINITY;  // already applied by the index list
+    L.use_region = 0;
+    L.walk_only = walk_only;
+    if (!ring) {
+        ring = S.hball;
+        ring_next = &S.hnext;
+        if (threadIdx.x == 0) S.hnext = 0;
+        if (threadIdx.x < geom::NHOLD) S.hball[threadIdx.x] = -1;
+    }
+    __syncthreads();
+    // each wave pulls spheres and keeps its own best
+    double wd = INFINITY, wlb = INFINITY, wx[3] = {0.0, 0.0, 0.0};
+    int64_t wi = INT64_MAX;
+    int wk = 0, wnd = 1;
+    double wlow = INFINITY;
+    geom::Holders hold{ring, ring_next, prof ? prof + RP_LN_EARLY : nullptr};  // shared by the waves, reset each pass
+    const int w = wid();
+    // each wave takes `pull` candidates at a time: lanes load them and their
+    // lower bounds together, then the survivors are searched in list order
+    // (re-pruned against the bound as it shrinks)
+    const int pull = ring_next == &S.hnext ? 16 : TEAM_PULL;  // a team spreads the list thinner
+    const unsigned long long t_pull = prof ? wall_clock64() : 0ull;
+    for (int guard = 0; guard < (1 << 30); ++guard) {
+        int k0 = 0;
+        if (lane() == 0) k0 = atomicAdd(counter, pull);
+        k0 = __shfl(k0, 0, 64);
+        if (k0 >= len) break;
+        const int64_t kl = (int64_t)k0 + lane();
+        const bool have = lane() < pull && kl < len;
+        const int64_t myi = have ? list[kl] : 0;
+        double mylb = INFINITY, myprune = INFINITY;  // tie-break key, pruning bound
+        if (have) {
+            const double *pp = p4 + 4 * myi;
+            mylb = fabs(geom::dist3(q, pp) - fabs(pp[3]));
+            myprune = myi == deepest ? mylb : dist_outside_ball(q, pp, fabs(pp[3]), pdeep, Rdeep);
+        }
+        unsigned long long pending = __ballot(have);
+        int ring_seen = -1;
+        while (pending) {
+            {
+                // the recent holders first, for the pending candidates together,
+                // whenever the ring has taken new entries: lane l tests candidate
+                // l % pull against holder share l / pull of the ring (a holder
+                // proves that the sphere has no uncovered point within the
+                // bound; the bound only shrinks afterwards)
+                const int shares = 64 / pull, per = (geom::NHOLD + shares - 1) / shares;
+                int rn = 0;
+                if (lane() == 0) rn = __hip_atomic_load(ring_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                rn = __shfl(rn, 0, 64);
+                if (rn != ring_seen) {
+                    ring_seen = rn;
+                    unsigned long long cb = 0;
+                    if (lane() == 0) cb = __hip_atomic_load(bound_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const double cur = __longlong_as_double((long long)__shfl(cb, 0, 64));
+                    const int cj = lane() % pull, hg = lane() / pull;
+                    const int64_t ci = __shfl(myi, cj, 64);
+                    int hit = 0;
+                    if ((pending >> cj) & 1ull) {
+                        const double *pc = p4 + 4 * ci;
+                        const double oc[3] = {pc[0], pc[1], pc[2]};
+                        const double rc = fabs(pc[3]);
+                        Balls Rg = L;
+                        if (!geom::set_region(Rg, oc, rc, q, cur * (1.0 + 1e-12) + 1e-15))
+                            hit = 1;
+                        else
+                            hit = geom::held_by(Rg, oc, rc, ring + hg * per,
+                                                max(0, min(per, geom::NHOLD - hg * per)));
+                    }
+                    const unsigned long long hb = __ballot(hit);
+                    unsigned long long held = 0;
+                    for (int k = 0; k < shares; ++k) held |= hb >> (k * pull);
+                    held &= (1ull << pull) - 1ull;
+                    if (prof && lane() == 0 && (pending & held))
+                        atomicAdd(&prof[RP_PRE_HELD], (unsigned long long)__popcll(pending & held));
+                    pending &= ~held;
+                    if (!pending) break;
+                }
+            }
+            unsigned long long cb = 0;
+            if (lane() == 0) cb = __hip_atomic_load(bound_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const double cur = __longlong_as_double((long long)__shfl(cb, 0, 64));  // wave-uniform
+            // prune only clearly worse spheres: exact ties must reach the tie-break
+            pending &= __ballot(!(myprune > cur * (1.0 + 1e-12) + 1e-15));
+            if (!pending) break;
+            const int src = __ffsll((long long)pending) - 1;
+            pending &= pending - 1ull;
+            const int64_t i = __shfl(myi, src, 64);
+            const double lbi = __shfl(mylb, src, 64);
+            const double *p = p4 + 4 * i;
+            double d, x[3];
+            if (prof && lane() == 0) atomicAdd(&prof[RP_SEARCHES], 1ull);
+            int kk = geom::lazy_nearest(L, p, fabs(p[3]), q, cur * (1.0 + 1e-12) + 1e-15, kp[w], kid[w],
+                                        flist + (int64_t)w * fcap, fcap, &d, x, &hold);
+            if (kk < 0) {
+                // a capped search proved only that this sphere has no uncovered
+                // point nearer than d (a lower bound); it matters only if the
+                // final answer is farther than that
+                wlow = fmin(wlow, d);
+                continue;
+            }
+            if (kk && better(d, i != deepest, lbi, i, wd, wnd, wlb, wi)) {
+                wd = d;
+                wnd = i != deepest;
+                wlb = lbi;
+                wi = i;
+                wk = kk;
+                wx[0] = x[0];
+                wx[1] = x[1];
+                wx[2] = x[2];
+                if (lane() == 0)
+                    atomicMin(bound_bits, (unsigned long long)__double_as_longlong(d));
+            }
+        }
+    }
+    if (prof && lane() == 0) atomicAdd(&prof[RP_T_PULL], wall_clock64() - t_pull);
+    if (lane() == 0) {
+        S.wlow[w] = wlow;
+        S.wd[w] = wd;
+        S.wnd[w] = wnd;
+        S.wlb[w] = wlb;
+        S.wi[w] = wi;
+        S.wk[w] = wk;
+        S.wx[w][0] = wx[0];
+        S.wx[w][1] = wx[1];
+        S.wx[w][2] = wx[2];
+    }
+}
+
+// The best of the waves' answers (kind 0: none) and their lowest capped bound.
+template <int NW>
+__device__ inline GroupBest group_best(const Shared<NW> &S) {
+    GroupBest gb;
+    gb.kind = 0;
+    gb.low = INFINITY;
+    int bw = -1;
+    for (int v = 0; v < NW; ++v) {
+        gb.low = fmin(gb.low, S.wlow[v]);
+        if (!S.wk[v]) continue;
+        if (bw < 0 || better(S.wd[v], S.wnd[v], S.wlb[v], S.wi[v], S.wd[bw], S.wnd[bw], S.wlb[bw], S.wi[bw])) bw = v;
+    }
+    if (bw >= 0) {
+        gb.d = S.wd[bw];
+        gb.nd = S.wnd[bw];
+        gb.lb = S.wlb[bw];
+        gb.i = S.wi[bw];
+        gb.kind = S.wk[bw];
+        gb.x[0] = S.wx[bw][0];
+        gb.x[1] = S.wx[bw][1];
+        gb.x[2] = S.wx[bw][2];
+    }
+    return gb;
+}
+
+// a = the better of a and b (by `better`), lowest capped bound of both
+__device__ inline void merge_best(GroupBest &a, const GroupBest &b) {
+    a.low = fmin(a.low, b.low);
+    if (b.kind && (!a.kind || better(b.d, b.nd, b.lb, b.i, a.d, a.nd, a.lb, a.i))) {
+        const double low = a.low;
+        a = b;
+        a.low = low;
+    }
+}
+
+// A helper group's part of a posted minimum-radius pass (job J): pull, then
+// store the group's best in its slot.
+template <int NW>
+__device__ void rmin_pull_job(Job *J, const double *p4, const int64_t *list, Cap (*kp)[geom::KMAX],
+                              int64_t (*kid)[geom::KMAX], int32_t *flist, int fcap, Shared<NW> &S, GroupBest *slot,
+                              unsigned long long *prof, int walk_only) {
+    const double q[3] = {J->q[0], J->q[1], J->q[2]};
+    const int64_t N = J->N;
+    rmin_pull<NW>(q, p4, J->tie, list, J->len, list + (N + 1), J->nl, J->deepest, J->Rdeep, &J->counter,
+                  &J->bound_bits, kp, kid, flist, fcap, S, prof, walk_only, J->hring, &J->hnext);
+    __syncthreads();
+    const GroupBest gb = group_best(S);
+    if (threadIdx.x == 0) *slot = gb;
+}
+
+template <int NW>
+__device__ __noinline__ int rmin_block(const double *q, int sigma, const double *p4, const double *W, int64_t N, double tol,
                                  double tie, int64_t *list, Cap (*kp)[geom::KMAX], int64_t (*kid)[geom::KMAX],
                                  int32_t *flist, int fcap,
                                  Shared<NW> &S, double *r_out, double *x_out, int64_t *sphere_out,
-                                 unsigned long long *prof = nullptr, int walk_only = 0) {
+                                 unsigned long long *prof = nullptr, int walk_only = 0,
+                                 const Team *team = nullptr) {
     const int tid = threadIdx.x;
     const int BS = NW * 64;
     unsigned long long tmark = (prof && tid == 0) ? wall_clock64() : 0ull;
@@ -360,147 +712,54 @@ __device__ inline int rmin_block(const double *q, int sigma, const double *p4, c
             prof[RP_LIST_LEN] += (unsigned long long)len;
             prof[RP_LOCAL_LEN] += (unsigned long long)nl;
         }
-        Balls L;
-        L.p4 = p4;
-        L.N = nl;
-        L.idx = lset;
-        L.has_extra = 0;
-        L.tol = tie;  // contour of the balls shrunk by the uniqueness tolerance only
-        L.skip = -1;
-        L.lq[0] = q[0];
-        L.lq[1] = q[1];
-        L.lq[2] = q[2];
-        L.lb = INFINITY;  // already applied by the index list
-        L.use_region = 0;
-        L.walk_only = walk_only;
+        int *counter = &S.counter;
+        unsigned long long *bbits = &S.bound_bits;
         if (tid == 0) {
             S.counter = 0;
             S.bound_bits = __double_as_longlong(bound);
-            S.hnext = 0;
         }
-        if (tid < geom::NHOLD) S.hball[tid] = -1;
+        const bool post = team && len > 32;  // a short list stays with this group
+        if (post) {
+            // post the pass on the board; every group pulls from its counter
+            Job *J = team->job;
+            if (tid == 0) {
+                J->type = J_RMIN;
+                J->counter = 0;
+                J->bound_bits = __double_as_longlong(bound);
+                J->q[0] = q[0];
+                J->q[1] = q[1];
+                J->q[2] = q[2];
+                J->Rdeep = Rdeep;
+                J->tie = tie;
+                J->N = N;
+                J->len = len;
+                J->nl = nl;
+                J->deepest = deepest;
+                J->hnext = 0;
+            }
+            if (tid < geom::NHOLD) J->hring[tid] = -1;
+            counter = &J->counter;
+            bbits = &J->bound_bits;
+            team_sync();
+        }
+        rmin_pull<NW>(q, p4, tie, list, len, lset, nl, deepest, Rdeep, counter, bbits, kp, kid, flist, fcap, S, prof,
+                      walk_only, post ? team->job->hring : nullptr, post ? &team->job->hnext : nullptr);
         __syncthreads();
-        // each wave pulls spheres and keeps its own best
-        double wd = INFINITY, wlb = INFINITY, wx[3] = {0.0, 0.0, 0.0};
-        int64_t wi = INT64_MAX;
-        int wk = 0, wnd = 1;
-        double wlow = INFINITY;
-        geom::Holders hold{S.hball, &S.hnext, prof ? prof + RP_LN_EARLY : nullptr};  // shared by the waves, reset each pass
-        const int w = wid();
-        // each wave takes PULL candidates at a time: lanes load them and their
-        // lower bounds together, then the survivors are searched in list order
-        // (re-pruned against the bound as it shrinks)
-        constexpr int PULL = 16;
-        const unsigned long long t_pull = prof ? wall_clock64() : 0ull;
-        for (int guard = 0; guard < (1 << 30); ++guard) {
-            int k0 = 0;
-            if (lane() == 0) k0 = atomicAdd(&S.counter, PULL);
-            k0 = __shfl(k0, 0, 64);
-            if (k0 >= len) break;
-            const int64_t kl = (int64_t)k0 + lane();
-            const bool have = lane() < PULL && kl < len;
-            const int64_t myi = have ? list[kl] : 0;
-            double mylb = INFINITY, myprune = INFINITY;  // tie-break key, pruning bound
-            if (have) {
-                const double *pp = p4 + 4 * myi;
-                mylb = fabs(geom::dist3(q, pp) - fabs(pp[3]));
-                myprune = myi == deepest ? mylb : dist_outside_ball(q, pp, fabs(pp[3]), pdeep, Rdeep);
-            }
-            unsigned long long pending = __ballot(have);
-            {
-                // the recent holders first, for the PULL candidates together:
-                // lane l tests candidate l % PULL against a quarter of the ring
-                // (a holder proves that the sphere has no uncovered point within
-                // the bound; the bound only shrinks afterwards)
-                static_assert(PULL == 16 && geom::NHOLD % 4 == 0, "four holder groups per candidate");
-                unsigned long long cb = 0;
-                if (lane() == 0) cb = __hip_atomic_load(&S.bound_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                const double cur = __longlong_as_double((long long)__shfl(cb, 0, 64));
-                const int cj = lane() & (PULL - 1), hg = lane() / PULL;
-                const int64_t ci = __shfl(myi, cj, 64);
-                int hit = 0;
-                if ((pending >> cj) & 1ull) {
-                    const double *pc = p4 + 4 * ci;
-                    const double oc[3] = {pc[0], pc[1], pc[2]};
-                    const double rc = fabs(pc[3]);
-                    Balls Rg = L;
-                    if (!geom::set_region(Rg, oc, rc, q, cur * (1.0 + 1e-12) + 1e-15))
-                        hit = 1;
-                    else
-                        hit = geom::held_by(Rg, oc, rc, S.hball + hg * (geom::NHOLD / 4), geom::NHOLD / 4);
-                }
-                const unsigned long long hb = __ballot(hit);
-                const unsigned long long held = (hb | (hb >> 16) | (hb >> 32) | (hb >> 48)) & 0xFFFFull;
-                if (prof && lane() == 0 && (pending & held)) atomicAdd(&prof[RP_PRE_HELD], (unsigned long long)__popcll(pending & held));
-                pending &= ~held;
-            }
-            while (pending) {
-                unsigned long long cb = 0;
-                if (lane() == 0) cb = __hip_atomic_load(&S.bound_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                const double cur = __longlong_as_double((long long)__shfl(cb, 0, 64));  // wave-uniform
-                // prune only clearly worse spheres: exact ties must reach the tie-break
-                pending &= __ballot(!(myprune > cur * (1.0 + 1e-12) + 1e-15));
-                if (!pending) break;
-                const int src = __ffsll((long long)pending) - 1;
-                pending &= pending - 1ull;
-                const int64_t i = __shfl(myi, src, 64);
-                const double lbi = __shfl(mylb, src, 64);
-                const double *p = p4 + 4 * i;
-                double d, x[3];
-                if (prof && lane() == 0) atomicAdd(&prof[RP_SEARCHES], 1ull);
-                int kk = geom::lazy_nearest(L, p, fabs(p[3]), q, cur * (1.0 + 1e-12) + 1e-15, kp[w], kid[w],
-                                            flist + (int64_t)w * fcap, fcap, &d, x, &hold);
-                if (kk < 0) {
-                    // a capped search proved only that this sphere has no uncovered
-                    // point nearer than d (a lower bound); it matters only if the
-                    // final answer is farther than that
-                    wlow = fmin(wlow, d);
-                    continue;
-                }
-                if (kk && better(d, i != deepest, lbi, i, wd, wnd, wlb, wi)) {
-                    wd = d;
-                    wnd = i != deepest;
-                    wlb = lbi;
-                    wi = i;
-                    wk = kk;
-                    wx[0] = x[0];
-                    wx[1] = x[1];
-                    wx[2] = x[2];
-                    if (lane() == 0)
-                        atomicMin(&S.bound_bits, (unsigned long long)__double_as_longlong(d));
-                }
-            }
-        }
-        if (prof && lane() == 0) atomicAdd(&prof[RP_T_PULL], wall_clock64() - t_pull);
-        if (lane() == 0) {
-            S.wlow[w] = wlow;
-            S.wd[w] = wd;
-            S.wnd[w] = wnd;
-            S.wlb[w] = wlb;
-            S.wi[w] = wi;
-            S.wk[w] = wk;
-            S.wx[w][0] = wx[0];
-            S.wx[w][1] = wx[1];
-            S.wx[w][2] = wx[2];
-        }
-        __syncthreads();
-        int bw = -1;
-        for (int v = 0; v < NW; ++v) {
-            if (!S.wk[v]) continue;
-            if (bw < 0 || better(S.wd[v], S.wnd[v], S.wlb[v], S.wi[v], S.wd[bw], S.wnd[bw], S.wlb[bw], S.wi[bw]))
-                bw = v;
+        GroupBest gb = group_best(S);
+        if (post) {
+            if (tid == 0) team->best[0] = gb;
+            team_sync();  // every group has stored its best
+            for (int g = 1; g < team->groups; ++g) merge_best(gb, team->best[g]);
         }
         int res = -1;
-        double low = INFINITY;
-        for (int v = 0; v < NW; ++v) low = fmin(low, S.wlow[v]);
-        const int numeric = bw >= 0 ? (low < S.wd[bw]) : (low < INFINITY);
-        if (bw >= 0 && !numeric) {
-            *r_out = S.wd[bw];
-            x_out[0] = S.wx[bw][0];
-            x_out[1] = S.wx[bw][1];
-            x_out[2] = S.wx[bw][2];
-            *sphere_out = S.wi[bw];
-            res = S.wk[bw];
+        const int numeric = gb.kind ? (gb.low < gb.d) : (gb.low < INFINITY);
+        if (gb.kind && !numeric) {
+            *r_out = gb.d;
+            x_out[0] = gb.x[0];
+            x_out[1] = gb.x[1];
+            x_out[2] = gb.x[2];
+            *sphere_out = gb.i;
+            res = gb.kind;
         }
         __syncthreads();
         lap(RP_T_SEARCH);

@@ -435,13 +435,13 @@ __device__ inline int wave_list_caps(const Balls &B, const double *o, double r, 
 // squared test only skips balls clearly apart, cap_of decides the rest.
 __device__ inline void wave_cover_list(const Balls &B, const double *o, double r, const double *v, double *mx,
                                        int64_t *arg, int *whole, int32_t *cl, int ccap, int *cnt_out, int *ecap,
-                                       int64_t *argpos) {
+                                       int64_t *argpos, int64_t fb = 0, int64_t fe = -1) {
     const int lane = threadIdx.x & 63;
     double best = -INFINITY;
     int64_t bi = INT64_MAX, bp = INT64_MAX;
     int wh = 0, ec = 0, cnt = 0;
-    const int64_t n = ball_count(B);
-    for (int64_t f0 = 0; f0 < n; f0 += 64) {
+    const int64_t n = fe < 0 ? ball_count(B) : fe;  // balls [fb, n) of B
+    for (int64_t f0 = fb; f0 < n; f0 += 64) {
         const int64_t f = f0 + lane;
         int take = 0;
         double m = -INFINITY;
@@ -487,6 +487,10 @@ __device__ inline void wave_cover_list(const Balls &B, const double *o, double r
     *cnt_out = cnt;
 }
 
+__device__ inline int lazy_exist_rest(const Balls &B0, const double *o, double r, const double *vh, Cap *kp,
+                                      int64_t *kid, int32_t *cl, int ccap, double *x, unsigned long long *walks,
+                                      double mx, int64_t arg, int whole, int ncl, int ecap, int64_t argpos);
+
 // Exact: does sphere (o, r) have a point no ball covers?  Writes one (nudged
 // off the rim it was found on) to x.  kp: this wave's LDS scratch (KMAX caps),
 // kid: their ball indices.  hint orders the search only.
@@ -529,6 +533,18 @@ __device__ inline int lazy_exist(const Balls &B0, const double *o, double r, con
     int ncl = 0, ecap = 0;
     int64_t argpos = 0;
     wave_cover_list(B, o, r, vh, &mx, &arg, &whole, cl, ccap, &ncl, &ecap, &argpos);
+    return lazy_exist_rest(B, o, r, vh, kp, kid, cl, ccap, x, walks, mx, arg, whole, ncl, ecap, argpos);
+}
+
+// lazy_exist after its first cover test at direction vh: margin mx at ball
+// arg (position argpos in the list), whole-sphere holder found, the ncl balls
+// meeting the sphere listed in cl (when ncl <= ccap), the extra ball meets it
+// (ecap).
+__device__ inline int lazy_exist_rest(const Balls &B0, const double *o, double r, const double *vh, Cap *kp,
+                                      int64_t *kid, int32_t *cl, int ccap, double *x, unsigned long long *walks,
+                                      double mx, int64_t arg, int whole, int ncl, int ecap, int64_t argpos) {
+    const int lane = threadIdx.x & 63;
+    Balls B = B0;
     if (whole) return ST_NONE;
     if (!(mx > COVER_EPS)) {
         for (int j = 0; j < 3; ++j) x[j] = o[j] + r * vh[j];
@@ -705,7 +721,7 @@ __device__ inline int set_region(Balls &B, const double *o, double r, const doub
 __device__ inline bool held_by(const Balls &B, const double *o, double r, const int64_t *ring, int nh) {
     if (!B.use_region) return false;
     for (int j = 0; j < nh; ++j) {
-        const int64_t f = __hip_atomic_load(&ring[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const int64_t f = __hip_atomic_load(&ring[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (f < 0 || f >= ball_count(B)) continue;
         Cap ch;
         const int st = cap_of(B, f, o, r, ch);
@@ -715,12 +731,12 @@ __device__ inline bool held_by(const Balls &B, const double *o, double r, const 
 }
 
 // Recently seen balls that held a whole search region (ball indices, -1
-// empty): a ring of NHOLD entries in LDS shared by the wavefronts of a
-// work-group.  Entries may be replaced while another wave reads them; any
+// empty): a ring of NHOLD entries shared by the wavefronts of a work-group
+// (LDS) or of a team of groups (global memory).  Entries may be replaced while another wave reads them; any
 // ball index read is a valid ball, and the holding test is exact for it.
 constexpr int NHOLD = 32;
 struct Holders {
-    int64_t *h;  // NHOLD entries (LDS)
+    int64_t *h;  // NHOLD entries
     int *next;   // ring position (LDS)
     // optional search profile: early, first, loop, rounds, fallback, first
     // ticks, loop ticks, fallback ticks, fallback caps, stalled rounds, early
@@ -732,7 +748,7 @@ struct Holders {
     __device__ void push(int64_t f) {
         if ((threadIdx.x & 63) == 0) {
             const int slot = atomicAdd(next, 1) & (NHOLD - 1);
-            __hip_atomic_store(&h[slot], f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_store(&h[slot], f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 };

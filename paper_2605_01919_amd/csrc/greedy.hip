@@ -71,7 +71,20 @@ struct GInst {
     int64_t n, m;
     int profile;             // record the finer sub-phase split (while timing is enabled)
     int walk_only;           // exact searches take the exhaustive rim walk (SDFI_OPT_EXHAUSTIVE)
+    blk::Team team;          // several groups on this instance (team.groups > 1, a cooperative launch)
 };
+
+// the cap lists of this group's waves for the exhaustive searches (NW lists
+// of fcap entries per group), and this wave's own
+template <int NW>
+__device__ inline int32_t *group_flist(const GInst &I) {
+    const int g = I.team.groups > 1 ? (int)blockIdx.x : 0;
+    return I.flist + (int64_t)g * NW * I.fcap;
+}
+template <int NW>
+__device__ inline int32_t *wave_flist(const GInst &I) {
+    return group_flist<NW>(I) + (int64_t)blk::wid() * I.fcap;
+}
 
 template <int NW>
 struct StepShared {
@@ -82,6 +95,7 @@ struct StepShared {
     int status;
     int fail;
     int counter;
+    int rt, rfail;  // reval_group: the sphere taken, the failure flag seen
 };
 
 __device__ inline bool in_domain(const double *w, const double *dlo, const double *dhi, double tol) {
@@ -131,68 +145,171 @@ __device__ inline void rim_hint(const double *o, double r, const double *q, doub
     for (int j = 0; j < 3; ++j) h[j] = o[j] + r * (c1 * u[j] + r1 * t[j] / tn);
 }
 
-// Exact re-search of the threatened spheres with the ball (q, s) added, waves
-// in parallel; results into I.pend.  SH.fail = 1 if some sphere has no
-// uncovered point left (with `keep_going` the search continues and such
+// The calling group's share of the exact re-searches of the threatened
+// spheres I.list[0..nthr) with the ball (q, s) added: waves take spheres from
+// *counter; results into I.pend; *fail set if a sphere has no uncovered point
+// left (without `keep_going` the waves then stop taking spheres; with it such
 // spheres keep their old witness).
 template <int NW>
-__device__ void revalidate(const GInst &I, int64_t N, const double *q, double s, int64_t nthr, double tol,
-                           StepShared<NW> &SH, bool keep_going) {
-    constexpr int GBS = NW * 64;
+__device__ __noinline__ void reval_part(const GInst &I, int64_t N, const double *q, double s, int64_t nthr, double tol,
+                           StepShared<NW> &SH, bool keep_going, int *counter, int *fail) {
     const int w = blk::wid(), ln = blk::lane();
+    geom::Balls B;
+    B.p4 = I.CP;
+    B.N = N;
+    B.extra[0] = q[0];
+    B.extra[1] = q[1];
+    B.extra[2] = q[2];
+    B.extra[3] = s;
+    B.has_extra = 1;
+    B.tol = tol;
+    B.lb = INFINITY;
+    B.idx = nullptr;
+    B.use_region = 0;
+    B.walk_only = I.walk_only;
+    int32_t *fl = wave_flist<NW>(I);
+    for (int64_t guard = 0; guard <= nthr; ++guard) {
+        int t = 0;
+        if (ln == 0) t = atomicAdd(counter, 1);
+        t = __shfl(t, 0, 64);
+        if (t >= nthr) break;
+        int fv = 0;
+        if (ln == 0) fv = __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (__shfl(fv, 0, 64) && !keep_going) break;  // wave-uniform
+        int64_t c = I.list[t];
+        B.skip = c;
+        const double *p = I.CP + 4 * c;
+        double x[3], hint[3];
+        rim_hint(p, fabs(p[3]), q, fabs(s) - tol, I.CW + 3 * c, hint);
+        int st = geom::lazy_exist_call(B, p, fabs(p[3]), hint, SH.kp[w], SH.kid[w], fl, I.fcap, x,
+                                       &I.counts[C_WALKS]);
+        if (ln == 0) {
+            atomicAdd(&I.counts[C_SEARCH], 1ull);
+            if (st == geom::ST_NUMERIC) atomicAdd(&I.counts[C_NUMERIC], 1ull);
+            bool ok = st == geom::ST_FOUND;
+            if (!ok) atomicOr(fail, 1);
+            for (int j = 0; j < 3; ++j) I.pend[3 * t + j] = ok ? x[j] : I.CW[3 * c + j];
+        }
+    }
+}
+
+// A team group's share of the re-searches: the group takes one threatened
+// sphere at a time from *counter and searches it with all its waves
+// (group_exist); otherwise as reval_part.
+template <int NW>
+__device__ __noinline__ void reval_group(const GInst &I, int64_t N, const double *q, double s, int64_t nthr,
+                                         double tol, StepShared<NW> &SH, bool keep_going, int *counter, int *fail) {
+    geom::Balls B;
+    B.p4 = I.CP;
+    B.N = N;
+    B.extra[0] = q[0];
+    B.extra[1] = q[1];
+    B.extra[2] = q[2];
+    B.extra[3] = s;
+    B.has_extra = 1;
+    B.tol = tol;
+    B.lb = INFINITY;
+    B.idx = nullptr;
+    B.use_region = 0;
+    B.walk_only = I.walk_only;
+    for (int64_t guard = 0; guard <= nthr; ++guard) {
+        if (threadIdx.x == 0) {
+            SH.rt = atomicAdd(counter, 1);
+            SH.rfail = __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        const int t = SH.rt, fv = SH.rfail;
+        __syncthreads();
+        if (t >= nthr || (fv && !keep_going)) break;  // group-uniform
+        const int64_t c = I.list[t];
+        B.skip = c;
+        const double *p = I.CP + 4 * c;
+        double x[3], hint[3];
+        rim_hint(p, fabs(p[3]), q, fabs(s) - tol, I.CW + 3 * c, hint);
+        const int st = blk::group_exist<NW>(B, p, fabs(p[3]), hint, SH.kp[0], SH.kid[0], group_flist<NW>(I), I.fcap,
+                                            x, &I.counts[C_WALKS], SH.S);
+        if (threadIdx.x == 0) {
+            atomicAdd(&I.counts[C_SEARCH], 1ull);
+            if (st == geom::ST_NUMERIC) atomicAdd(&I.counts[C_NUMERIC], 1ull);
+            const bool ok = st == geom::ST_FOUND;
+            if (!ok) atomicOr(fail, 1);
+            for (int j = 0; j < 3; ++j) I.pend[3 * t + j] = ok ? x[j] : I.CW[3 * c + j];
+        }
+    }
+}
+
+// Exact re-search of the threatened spheres with the ball (q, s) added:
+// several spheres go to the team's groups (each searched by a whole group);
+// without a team, a few spheres are searched one after another by the whole
+// group, more by the waves in parallel.  Results into I.pend, SH.fail = 1 if
+// some sphere has no uncovered point left.
+template <int NW>
+__device__ __noinline__ void revalidate(const GInst &I, int64_t N, const double *q, double s, int64_t nthr, double tol,
+                           StepShared<NW> &SH, bool keep_going) {
     if (threadIdx.x == 0) {
         SH.fail = 0;
         SH.counter = 0;
     }
     __syncthreads();
-    if (nthr > 0) {
-        geom::Balls B;
-        B.p4 = I.CP;
-        B.N = N;
-        B.extra[0] = q[0];
-        B.extra[1] = q[1];
-        B.extra[2] = q[2];
-        B.extra[3] = s;
-        B.has_extra = 1;
-        B.tol = tol;
-        B.lb = INFINITY;
-        B.idx = nullptr;
-        B.use_region = 0;
-        B.walk_only = I.walk_only;
-        for (int64_t guard = 0; guard <= nthr; ++guard) {
-            int t = 0;
-            if (ln == 0) t = atomicAdd(&SH.counter, 1);
-            t = __shfl(t, 0, 64);
-            if (t >= nthr) break;
-            int fl = 0;
-            if (ln == 0) fl = __hip_atomic_load(&SH.fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (__shfl(fl, 0, 64) && !keep_going) break;  // wave-uniform
-            int64_t c = I.list[t];
-            B.skip = c;
-            const double *p = I.CP + 4 * c;
-            double x[3], hint[3];
-            rim_hint(p, fabs(p[3]), q, fabs(s) - tol, I.CW + 3 * c, hint);
-            int st = geom::lazy_exist_call(B, p, fabs(p[3]), hint, SH.kp[w], SH.kid[w], I.flist + (int64_t)w * I.fcap,
-                                           I.fcap, x, &I.counts[C_WALKS]);
-            if (ln == 0) {
-                atomicAdd(&I.counts[C_SEARCH], 1ull);
-                if (st == geom::ST_NUMERIC) atomicAdd(&I.counts[C_NUMERIC], 1ull);
-                bool ok = st == geom::ST_FOUND;
-                if (!ok) atomicOr(&SH.fail, 1);
-                for (int j = 0; j < 3; ++j) I.pend[3 * t + j] = ok ? x[j] : I.CW[3 * c + j];
-            }
+    if (nthr <= 0) return;
+    if (I.team.groups > 1 && nthr > 1) {
+        blk::Job *J = I.team.job;
+        if (threadIdx.x == 0) {
+            J->type = blk::J_REVAL;
+            J->counter = 0;
+            J->fail = 0;
+            J->keep_going = keep_going ? 1 : 0;
+            J->q[0] = q[0];
+            J->q[1] = q[1];
+            J->q[2] = q[2];
+            J->s = s;
+            J->N = N;
+            J->nthr = nthr;
         }
+        blk::team_sync();
+        reval_group<NW>(I, N, q, s, nthr, tol, SH, keep_going, &J->counter, &J->fail);
+        blk::team_sync();
+        if (threadIdx.x == 0) SH.fail = __hip_atomic_load(&J->fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else if (nthr <= NW / 4 || I.team.groups > 1) {
+        reval_group<NW>(I, N, q, s, nthr, tol, SH, keep_going, &SH.counter, &SH.fail);
+    } else {
+        reval_part<NW>(I, N, q, s, nthr, tol, SH, keep_going, &SH.counter, &SH.fail);
     }
     __syncthreads();
+}
+
+// A helper group of a team: work on the jobs group 0 posts until it posts
+// J_EXIT.
+template <int NW>
+__device__ __noinline__ void helper_loop(const GInst &I, double tol, StepShared<NW> &SH) {
+    blk::Job *J = I.team.job;
+    for (;;) {
+        blk::team_sync();
+        const int type = __hip_atomic_load(&J->type, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (type == blk::J_EXIT) return;
+        if (type == blk::J_RMIN) {
+            blk::rmin_pull_job<NW>(J, I.CP, I.list, SH.kp, SH.kid, group_flist<NW>(I), I.fcap, SH.S,
+                                   I.team.best + blockIdx.x, I.profile ? I.counts + C_RP0 : nullptr, I.walk_only);
+        } else if (type == blk::J_REVAL) {
+            const double q[3] = {J->q[0], J->q[1], J->q[2]};
+            reval_group<NW>(I, J->N, q, J->s, J->nthr, tol, SH, J->keep_going != 0, &J->counter, &J->fail);
+        }
+        blk::team_sync();
+    }
 }
 
 template <int NW>
 __global__ __launch_bounds__(NW * 64) void greedy_kernel(const GInst *insts, double tol, double tie, double dlo0,
                                                          double dlo1, double dlo2, double dhi0, double dhi1,
-                                                         double dhi2) {
+                                                         double dhi2, int groups) {
     constexpr int GBS = NW * 64;
     __shared__ StepShared<NW> SH;
-    const GInst I = insts[blockIdx.x];
+    // groups > 1: all groups of the launch work on instance 0 (a team)
+    const GInst I = insts[groups > 1 ? 0 : blockIdx.x];
+    if (groups > 1 && blockIdx.x > 0) {
+        helper_loop<NW>(I, tol, SH);
+        return;
+    }
     const int tid = threadIdx.x;
     const int w = blk::wid(), ln = blk::lane();
     const double dlo[3] = {dlo0, dlo1, dlo2}, dhi[3] = {dhi0, dhi1, dhi2};
@@ -296,35 +413,23 @@ __global__ __launch_bounds__(NW * 64) void greedy_kernel(const GInst *insts, dou
                     sub(C_T_COVER);
                     double nw[3] = {cw[e][0], cw[e][1], cw[e][2]};
                     if (cov) {
-                        if (w == 0) {
-                            geom::Balls B;
-                            B.p4 = I.CP;
-                            B.N = N;
-                            B.has_extra = 0;
-                            B.tol = tol;
-                            B.skip = -1;
-                            B.lb = INFINITY;
-                            B.idx = nullptr;
-                            B.use_region = 0;
-                            B.walk_only = I.walk_only;
-                            double x[3];
-                            int st = geom::lazy_exist_call(B, q, r, cw[e], SH.kp[0], SH.kid[0], I.flist, I.fcap, x,
-                                                           &I.counts[C_WALKS]);
-                            if (ln == 0) {
-                                SH.status = st;
-                                SH.x[0] = x[0];
-                                SH.x[1] = x[1];
-                                SH.x[2] = x[2];
-                                atomicAdd(&I.counts[C_SEARCH], 1ull);
-                                if (st == geom::ST_NUMERIC) atomicAdd(&I.counts[C_NUMERIC], 1ull);
-                            }
+                        // the whole group runs the new sphere's exact search
+                        geom::Balls B;
+                        B.p4 = I.CP;
+                        B.N = N;
+                        B.has_extra = 0;
+                        B.tol = tol;
+                        B.skip = -1;
+                        B.lb = INFINITY;
+                        B.idx = nullptr;
+                        B.use_region = 0;
+                        B.walk_only = I.walk_only;
+                        const int st = blk::group_exist<NW>(B, q, r, cw[e], SH.kp[0], SH.kid[0], group_flist<NW>(I),
+                                                            I.fcap, nw, &I.counts[C_WALKS], SH.S);
+                        if (tid == 0) {
+                            atomicAdd(&I.counts[C_SEARCH], 1ull);
+                            if (st == geom::ST_NUMERIC) atomicAdd(&I.counts[C_NUMERIC], 1ull);
                         }
-                        __syncthreads();
-                        int st = SH.status;
-                        nw[0] = SH.x[0];
-                        nw[1] = SH.x[1];
-                        nw[2] = SH.x[2];
-                        __syncthreads();
                         sub(C_T_VNEW);
                         if (st != geom::ST_FOUND) continue;
                     }
@@ -364,7 +469,7 @@ __global__ __launch_bounds__(NW * 64) void greedy_kernel(const GInst *insts, dou
                         int64_t sph;
                         int kk = blk::rmin_block<NW>(q, sigma, I.CP, I.CW, N, tol, tie, I.list, SH.kp, SH.kid, I.flist,
                                                      I.fcap, SH.S, &rr, x, &sph, I.profile ? I.counts + C_RP0 : nullptr,
-                                                     I.walk_only);
+                                                     I.walk_only, groups > 1 ? &I.team : nullptr);
                         if (kk == -2 && tid == 0) atomicAdd(&I.counts[C_NUMERIC], 1ull);
                         if (kk > 0) {
                             val = sigma * rr;
@@ -435,6 +540,11 @@ __global__ __launch_bounds__(NW * 64) void greedy_kernel(const GInst *insts, dou
         __threadfence_block();
         __syncthreads();
         if (tid == 0) I.counts[C_T_RECORD] += wall_clock64() - t_mark;
+    }
+    if (groups > 1) {
+        // release the helper groups
+        if (tid == 0) __hip_atomic_store(&I.team.job->type, blk::J_EXIT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        blk::team_sync();
     }
     // final witnesses of the query spheres and of the samples
     for (int64_t c = n + tid; c < N; c += GBS) {
@@ -518,9 +628,10 @@ struct GBufs {
     int64_t *order;
     int64_t *seg;
     GInst *inst;
+    blk::Job *job;
+    blk::GroupBest *best;
 };
 
-// wavefronts per greedy work-group for these options
 // Work-groups of the greedy kernel with nw waves that the current device
 // keeps resident at once (occupancy x compute units), looked up once per
 // device.
@@ -551,7 +662,17 @@ int greedy_waves(const sdfi_options &o, int ninst = 1) {
     return slots > 0 && ninst > slots ? 4 : NW_DEFAULT;
 }
 
-GBufs carve_greedy(Carver &c, int64_t n, int64_t m, int ninst, int nw) {
+// Groups that share a single instance: o.groups, else 16; at most what the
+// device keeps resident (a cooperative launch needs every group resident).
+constexpr int TEAM_DEFAULT = 16;
+int team_request(const sdfi_options &o) { return o.groups > 0 ? o.groups : TEAM_DEFAULT; }
+int team_groups(const sdfi_options &o, int nw) {
+    const int slots = resident_groups(nw);
+    return std::max(1, std::min(team_request(o), slots));
+}
+
+// groups: work-groups per instance (a team when > 1, single instance only)
+GBufs carve_greedy(Carver &c, int64_t n, int64_t m, int ninst, int nw, int groups) {
     GBufs b;
     int64_t cap = n + m + 1;
     b.CP = c.take<double>(4 * cap);
@@ -560,12 +681,14 @@ GBufs carve_greedy(Carver &c, int64_t n, int64_t m, int ninst, int nw) {
     b.win = c.take<double>(3 * (n + 1));
     b.CSRC = c.take<int64_t>(cap);
     b.list = c.take<int64_t>(2 * (cap + ninst) + 2);
-    b.flist = c.take<int32_t>((int64_t)nw * (cap + ninst));
+    b.flist = c.take<int32_t>((int64_t)groups * nw * (cap + ninst));
     b.wstat = c.take<uint8_t>(n + 1);
     b.counts = c.take<unsigned long long>(C_NCOUNT * ninst);
     b.order = c.take<int64_t>(m + 1);
     b.seg = c.take<int64_t>(ninst + 1);
     b.inst = c.take<GInst>(ninst);
+    b.job = c.take<blk::Job>(1);
+    b.best = c.take<blk::GroupBest>(groups);
     return b;
 }
 
@@ -586,7 +709,7 @@ sdfi_status run_witnesses(const double *samples, int64_t n, double *w, uint8_t *
 
 size_t greedy_ws(int64_t n, int64_t m, const sdfi_options &o) {
     Carver c(nullptr, 0, true);
-    carve_greedy(c, n, m, 1, greedy_waves(o));
+    carve_greedy(c, n, m, 1, greedy_waves(o), team_request(o));
     Carver c2(nullptr, 0, true);
     size_t ord = order_ws(n, m, o);
     size_t cert = (o.flags & SDFI_OPT_CERTIFY) ? certify_ws(n + m, o) + 4 * (n + m) * 8 + 3 * (n + m) * 8 + 1024 : 0;
@@ -641,7 +764,8 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
     const int64_t n = soff[ninst], m = qoff[ninst];
     Carver c(ws, ws_bytes);
     const int nw = greedy_waves(o, ninst);
-    GBufs b = carve_greedy(c, n + ninst, m, ninst, nw);
+    const int groups = ninst == 1 ? team_groups(o, nw) : 1;
+    GBufs b = carve_greedy(c, n + ninst, m, ninst, nw, groups);
     if (!c.ok()) {
         set_error("workspace too small for the greedy interpolation");
         return SDFI_ERR_WORKSPACE;
@@ -754,6 +878,9 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
         g.counts = b.counts + C_NCOUNT * i;
         g.profile = timing_enabled() ? 1 : 0;
         g.walk_only = (o.flags & SDFI_OPT_EXHAUSTIVE) ? 1 : 0;
+        g.team.job = b.job;
+        g.team.best = b.best;
+        g.team.groups = groups;
         g.n = ni;
         g.m = mi;
         cpos += ni + mi;
@@ -766,13 +893,24 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
     });
     SDFI_HIP(hipMemcpyAsync(b.inst, hi.data(), sizeof(GInst) * ninst, hipMemcpyHostToDevice, st));
     KernelTimer tm("greedy", st);
-    if (nw == 4)
+    if (groups > 1) {
+        // one instance, `groups` work-groups: a cooperative launch (all resident)
+        const GInst *ip = b.inst;
+        double tol = o.tol, tie = o.tie_tol;
+        double d0 = o.domain_lo[0], d1 = o.domain_lo[1], d2 = o.domain_lo[2];
+        double d3 = o.domain_hi[0], d4 = o.domain_hi[1], d5 = o.domain_hi[2];
+        int gr = groups;
+        void *args[] = {&ip, &tol, &tie, &d0, &d1, &d2, &d3, &d4, &d5, &gr};
+        const void *fn = nw == 4 ? (const void *)greedy_kernel<4> : (const void *)greedy_kernel<NW_DEFAULT>;
+        SDFI_HIP(hipLaunchCooperativeKernel(fn, dim3(groups), dim3(nw * 64), args, 0, st));
+    } else if (nw == 4) {
         greedy_kernel<4><<<ninst, 4 * 64, 0, st>>>(b.inst, o.tol, o.tie_tol, o.domain_lo[0], o.domain_lo[1],
-                                                   o.domain_lo[2], o.domain_hi[0], o.domain_hi[1], o.domain_hi[2]);
-    else
+                                                   o.domain_lo[2], o.domain_hi[0], o.domain_hi[1], o.domain_hi[2], 1);
+    } else {
         greedy_kernel<NW_DEFAULT><<<ninst, NW_DEFAULT * 64, 0, st>>>(b.inst, o.tol, o.tie_tol, o.domain_lo[0],
                                                                      o.domain_lo[1], o.domain_lo[2], o.domain_hi[0],
-                                                                     o.domain_hi[1], o.domain_hi[2]);
+                                                                     o.domain_hi[1], o.domain_hi[2], 1);
+    }
     tm.stop();
     SDFI_HIP(hipGetLastError());
     std::vector<unsigned long long> cnt(C_NCOUNT * ninst);

@@ -33,7 +33,7 @@ class Options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("precision", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("tie_tol", ctypes.c_double), ("domain_lo", ctypes.c_double * 3),
                 ("domain_hi", ctypes.c_double * 3), ("grid", ctypes.c_int32), ("block_size", ctypes.c_int32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("groups", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -79,7 +79,7 @@ EXPORTS = ["sdfi_default_options", "sdfi_last_error", "sdfi_version", "sdfi_timi
            "sdfi_greedy_interpolate_batched", "sdfi_min_valid_radius", "sdfi_repair", "sdfi_greedy_backward"]
 
 
-def options(precision="fp32", grid=0, flags=0, tol=1e-6, tie_tol=1e-9, block_size=0):
+def options(precision="fp32", grid=0, flags=0, tol=1e-6, tie_tol=1e-9, block_size=0, groups=0):
     o = Options()
     lib().sdfi_default_options(ctypes.byref(o))
     o.precision = {"fp64": PREC_FP64, "fp32": PREC_FP32_FP64_RECHECK}[precision] if isinstance(precision, str) \
@@ -89,6 +89,7 @@ def options(precision="fp32", grid=0, flags=0, tol=1e-6, tie_tol=1e-9, block_siz
     o.tol = tol
     o.tie_tol = tie_tol
     o.block_size = block_size
+    o.groups = int(groups)
     return o
 
 
@@ -230,7 +231,7 @@ def sample_witnesses(samples):
 
 
 def greedy(samples, queries, order=None, grid=0, certify=False, input_check=False, sample_witness=False,
-           block_size=0, exhaustive=False):
+           block_size=0, exhaustive=False, groups=0):
     """Greedy interpolation.  Returns a dict of GPU tensors and the host report.
     exhaustive: the exact searches take their last-resort rim walk (testing)."""
     samples = _dev(samples, torch.float64, 4, "samples")
@@ -238,7 +239,7 @@ def greedy(samples, queries, order=None, grid=0, certify=False, input_check=Fals
     n, m = samples.shape[0], queries.shape[0]
     flags = (OPT_CERTIFY if certify else 0) | (OPT_INPUT_CHECK if input_check else 0)
     flags |= OPT_EXHAUSTIVE if exhaustive else 0
-    opt = options(grid=grid, flags=flags, block_size=block_size)
+    opt = options(grid=grid, flags=flags, block_size=block_size, groups=groups)
     dev = samples.device
     if order is not None:
         order = _dev(order, torch.int64, None, "order")

@@ -127,6 +127,22 @@ def test_greedy_block_size_gives_identical_results():
         assert r["n_violations_pairwise"] == 0 and r["n_violations_witness"] == 0
 
 
+@pytest.mark.parametrize("name", ["sphere6", "balls6"])
+def test_team_of_groups_gives_identical_results(name):
+    # one instance on several work-groups (a cooperative launch sharing the
+    # minimum-radius and re-validation searches) equals one work-group
+    w = CASES[name]()
+    s, q = dev(np.c_[w.points, w.values]), dev(w.queries)
+    print("team", name, flush=True)
+    one = sdfi.greedy(s, q, grid=w.grid, groups=1, certify=True)
+    for groups in (0, 3):
+        team = sdfi.greedy(s, q, grid=w.grid, groups=groups, certify=True)
+        rep = team["report"]
+        assert rep["n_violations_pairwise"] == 0 and rep["n_violations_witness"] == 0
+        for k in ("values", "kind", "active", "order"):
+            assert torch.equal(torch.nan_to_num(one[k].double(), nan=7.0), torch.nan_to_num(team[k].double(), nan=7.0)), (groups, k)
+
+
 def test_input_check_rejects_covered_sample():
     P = np.array([[0.2, 0.2, 0.2], [0.22, 0.2, 0.2], [0.6, 0.6, 0.6]])
     S = np.array([0.15, 0.05, 0.1])
