@@ -70,6 +70,15 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic_balls64.md")
 SWEEP_SOURCE = os.path.join(ROOT, "paper_2605_01919_amd", "csrc", "bounds.hip")
 
 
+# the greedy's named work counters (sdfi_counter_query), reported with --counters
+GREEDY_COUNTERS = (
+    "greedy_cover_ticks", "greedy_vnew_ticks", "greedy_threat_ticks", "greedy_reval_ticks", "greedy_threatened",
+    "rmin_scan_ticks", "rmin_ray_ticks", "rmin_list_ticks", "rmin_search_ticks", "rmin_calls", "rmin_passes",
+    "rmin_list_len", "rmin_local_len", "rmin_searches", "ln_early", "ln_first", "ln_loop", "ln_rounds",
+    "ln_fallback", "ln_first_ticks", "ln_loop_ticks", "ln_fallback_ticks", "ln_early_ticks", "rmin_wide_passes",
+    "rmin_open_passes", "rmin_pre_held", "rmin_pull_ticks", "exist_walks", "greedy_instance_max_ticks")
+
+
 def recorded_traffic():
     """HBM bytes per sweep launch from the recorded counter runs, or None when
     the sweep's source changed since they were taken."""
@@ -196,6 +205,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-repair", action="store_true")
     ap.add_argument("--copy-bytes", type=int, default=0)
+    ap.add_argument("--counters", action="store_true",
+                    help="run the greedy leg with the library's timers on and report its work counters")
     ap.add_argument("--csg", type=int, default=0,
                     help="only time the pseudo-SDF repair workload on a CSG^3 grid in parts (96: the full recipe)")
     ap.add_argument("--save", default=None, help="with --csg: save a seeded sample of the outputs (npz)")
@@ -276,8 +287,19 @@ def main():
         c1 = configs.by_name("sphere16")
         s1 = torch.tensor(np.c_[c1.points, c1.values], device=dev)
         q1 = torch.tensor(c1.queries, device=dev)
+        if args.counters:
+            sdfi.timing(True)
         g, gt = wall(lambda: sdfi.greedy(s1, q1, grid=c1.grid, certify=True))
         rep = g["report"]
+        counters = None
+        if args.counters:
+            khz = sdfi.counter_read("wall_clock_khz") or 100000
+            counters = {}
+            for name in GREEDY_COUNTERS:
+                v = sdfi.counter_read(name)
+                counters[name] = round(v / khz, 1) if name.endswith("_ticks") else v
+            sdfi.timing(False)
+            progress("greedy counters: " + json.dumps(counters))
         bad = rep["n_violations_pairwise"] + rep["n_violations_witness"]
         progress(f"greedy sphere16: {gt:.1f} s, {c1.m / gt:.0f} queries/s, violations {bad}, "
                  f"capped searches {rep['n_search_capped']}")
@@ -300,6 +322,10 @@ def main():
             "kinds": {"hi": rep["n_hi"], "lo": rep["n_lo"], "zero": rep["n_zero"], "rmin": rep["n_rmin"],
                       "coincident": rep["n_coincident"]},
             "backward_ms": round(bt * 1e3, 3)}
+        if counters is not None:
+            out["greedy"]["counters"] = counters
+            out["greedy"]["counters_basis"] = ("library work counters of the run (*_ticks: ms of the device clock, "
+                                               "summed over wavefronts for ln_* and rmin_pull_ticks)")
     if not args.no_greedy and not args.no_batched:
         inst = configs.batch(BATCH_COUNT, grids=BATCH_GRIDS)
         tens = [(torch.tensor(np.c_[x.points, x.values], device=dev), torch.tensor(x.queries, device=dev), x.grid)
