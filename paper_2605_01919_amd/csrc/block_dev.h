@@ -62,6 +62,15 @@ struct Shared {
     int gwhole[NW], gcnt[NW], gecap[NW];
     int gst;
     double gx[3];
+    // group_exist's rounds: wave 0's candidate directions (one per lane), the
+    // rim each lies on and its cap's ball, their cover margins and covering
+    // balls (found by all waves), the round's state
+    double cv[64][3];
+    double cmx[64];
+    int64_t carg[64], cself[64];
+    int crim[64];
+    unsigned long long cfound;
+    int gctl, gend, gfin;  // state after the walks, at the round's end, after the fallback
 };
 
 // Several work-groups on one instance (a cooperative launch): group 0 runs
@@ -102,6 +111,125 @@ struct Team {
 __device__ inline void team_sync() { cooperative_groups::this_grid().sync(); }
 
 __device__ inline int wid() { return threadIdx.x >> 6; }
+
+// geom::lazy_exist_rest for a whole work-group: wave 0 walks the subset's
+// rims as the one-wave search does; the cover tests of its candidate points
+// (one per lane that found a gap) are shared out over all waves; wave 0 then
+// takes them in lane order exactly as the one-wave search would (the first
+// uncovered one is the answer, else each covering cap joins the subset).
+// Every thread gets the status and the point.
+template <int NW>
+__device__ int group_exist_rest(const Balls &B0, const double *o, double r, const double *vh, Cap *kp, int64_t *kid,
+                                int32_t *cl, int ccap, double *x, unsigned long long *walks, double mx, int64_t arg,
+                                int whole, int ncl, int ecap, int64_t argpos, Shared<NW> &S) {
+    const int w = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    if (whole) return geom::ST_NONE;
+    if (!(mx > geom::COVER_EPS)) {
+        for (int j = 0; j < 3; ++j) x[j] = o[j] + r * vh[j];
+        return geom::ST_FOUND;
+    }
+    const bool compact = ncl <= ccap;
+    const Balls B = geom::search_balls(B0, cl, ncl, ccap, ecap);
+    if (compact) arg = argpos;
+    if (threadIdx.x == 0) {
+        kid[0] = arg;
+        geom::cap_of(B, arg, o, r, kp[0]);
+    }
+    int k = 1;  // wave 0's subset size
+    __syncthreads();
+    // state: 0 next round, 1 found (S.gx), 2 covered, 3 fall back
+    int state = 3;
+    for (int round = 0; round < (B.walk_only ? 0 : 4 * geom::KMAX); ++round) {
+        if (w == 0) {
+            int found, numeric, frim;
+            double mxp, myp;
+            geom::Rim R;
+            geom::subset_gap(kp, k, found, numeric, frim, R, mxp, myp);
+            const unsigned long long fm = __ballot(found);
+            const int anynum = geom::wor(numeric);
+            if (found) {
+                double v[3];
+                geom::rim_dir(R, mxp, myp, v);
+                S.cv[ln][0] = v[0];
+                S.cv[ln][1] = v[1];
+                S.cv[ln][2] = v[2];
+                S.crim[ln] = frim;
+                S.cself[ln] = kid[frim];
+            }
+            if (ln == 0) {
+                S.cfound = fm;
+                S.gctl = fm ? 0 : (anynum ? 3 : 2);
+            }
+        }
+        __syncthreads();
+        state = S.gctl;
+        const unsigned long long fm = S.cfound;
+        if (state) break;
+        for (int c = w; c < 64; c += NW) {
+            if (!((fm >> c) & 1ull)) continue;
+            const double v[3] = {S.cv[c][0], S.cv[c][1], S.cv[c][2]};
+            double m;
+            int64_t a;
+            int wh;
+            geom::wave_cover(B, o, r, v, S.cself[c], &m, &a, &wh);
+            if (ln == 0) {
+                S.cmx[c] = m;
+                S.carg[c] = a;
+            }
+        }
+        __syncthreads();
+        if (w == 0) {
+            int st = 0, added = 0;
+            for (int c = 0; c < 64 && !st; ++c) {
+                if (!((fm >> c) & 1ull)) continue;
+                if (!(S.cmx[c] > geom::COVER_EPS)) {
+                    double v[3] = {S.cv[c][0], S.cv[c][1], S.cv[c][2]};
+                    geom::nudge_off_rim(B, o, r, kp[S.crim[c]], v);
+                    if (ln == 0)
+                        for (int j = 0; j < 3; ++j) S.gx[j] = o[j] + r * v[j];
+                    st = 1;
+                    break;
+                }
+                const int64_t a = S.carg[c];
+                bool have = false;
+                for (int e = 0; e < k; ++e) have |= (kid[e] == a);
+                if (!have && k < geom::KMAX) {
+                    if (ln == 0) {
+                        kid[k] = a;
+                        geom::cap_of(B, a, o, r, kp[k]);
+                    }
+                    geom::wave_sync_lds();
+                    ++k;
+                    ++added;
+                }
+            }
+            if (!st && !added) st = 3;  // subset full or no progress: fall back
+            if (ln == 0) S.gend = st;
+        }
+        __syncthreads();
+        state = S.gend;
+        if (state) break;
+        state = 3;
+    }
+    if (state == 2) return geom::ST_NONE;
+    if (state == 3) {
+        if (w == 0) {
+            double xf[3];
+            const int st = geom::exist_fallback(B, o, r, cl, ccap, compact, xf, walks);
+            if (ln == 0) {
+                S.gfin = st == geom::ST_FOUND ? 1 : (st == geom::ST_NONE ? 2 : 4);
+                if (st == geom::ST_FOUND)
+                    for (int j = 0; j < 3; ++j) S.gx[j] = xf[j];
+            }
+        }
+        __syncthreads();
+        state = S.gfin;
+    }
+    // state 1: found at S.gx; 2: covered; 4: numeric
+    for (int j = 0; j < 3; ++j) x[j] = S.gx[j];
+    __syncthreads();
+    return state == 1 ? geom::ST_FOUND : (state == 2 ? geom::ST_NONE : geom::ST_NUMERIC);
+}
 
 // geom::lazy_exist for a whole work-group: the waves split the first cover
 // test (which also lists the balls that meet the sphere) over slices of the
@@ -185,23 +313,8 @@ __device__ __noinline__ int group_exist(const Balls &B, const double *o, double 
     }
     __threadfence_block();
     __syncthreads();
-    if (w == 0) {
-        const int st = geom::lazy_exist_rest(B, o, r, vh, kp, kid, cl, ccap, x, walks, mx, arg, whole,
-                                             fits ? total : ccap + 1, ecap, pos);
-        if ((threadIdx.x & 63) == 0) {
-            S.gst = st;
-            S.gx[0] = x[0];
-            S.gx[1] = x[1];
-            S.gx[2] = x[2];
-        }
-    }
-    __syncthreads();
-    const int st = S.gst;
-    x[0] = S.gx[0];
-    x[1] = S.gx[1];
-    x[2] = S.gx[2];
-    __syncthreads();
-    return st;
+    return group_exist_rest<NW>(B, o, r, vh, kp, kid, cl, ccap, x, walks, mx, arg, whole, fits ? total : ccap + 1,
+                                ecap, pos, S);
 }
 __device__ inline int lane() { return threadIdx.x & 63; }
 

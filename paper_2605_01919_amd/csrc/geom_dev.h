@@ -536,6 +536,76 @@ __device__ inline int lazy_exist(const Balls &B0, const double *o, double r, con
     return lazy_exist_rest(B, o, r, vh, kp, kid, cl, ccap, x, walks, mx, arg, whole, ncl, ecap, argpos);
 }
 
+// Step 1 of a round of the lazy search: each lane walks rims lane and
+// lane + 64 of the working subset kp[0..k) and keeps the first gap it finds:
+// found, the rim's index frim, the rim R and the gap's midpoint (mxp, myp)
+// in its frame; numeric when a walk hit its step cap.
+__device__ inline void subset_gap(const Cap *kp, int k, int &found, int &numeric, int &frim, Rim &R, double &mxp,
+                                  double &myp) {
+    const int lane = threadIdx.x & 63;
+    const SubsetCaps sub{kp, k};
+    found = 0;
+    numeric = 0;
+    frim = -1;
+    mxp = 0.0;
+    myp = 0.0;
+    for (int e = lane; e < k && !found; e += 64) {
+        make_rim(kp[e], R);
+        double px, py;
+        int mv;
+        const int st = rim_walk(R, sub, e, 1.0, 0.0, 1, k + 4, &px, &py, &mv);
+        if (st == 1) {
+            found = 1;
+            frim = e;
+            gap_mid(R, kp, k, e, px, py, &mxp, &myp);
+        } else if (st == 2) {
+            numeric = 1;
+        }
+    }
+}
+
+// A verified uncovered direction v on the rim of cap `rim`: moved off that rim
+// (into the gap) by NUDGE when the moved point is still uncovered (one wave).
+__device__ inline void nudge_off_rim(const Balls &B, const double *o, double r, const Cap &rim, double *v) {
+    const double uv = dot3(rim.u, v);
+    const double tg[3] = {rim.u[0] - uv * v[0], rim.u[1] - uv * v[1], rim.u[2] - uv * v[2]};
+    const double tn = sqrt(dot3(tg, tg));
+    if (tn > 0.0) {
+        double w[3] = {v[0] - NUDGE * tg[0] / tn, v[1] - NUDGE * tg[1] / tn, v[2] - NUDGE * tg[2] / tn};
+        const double wn = sqrt(dot3(w, w));
+        w[0] /= wn;
+        w[1] /= wn;
+        w[2] /= wn;
+        double m2;
+        int64_t a2;
+        int wh2;
+        wave_cover(B, o, r, w, -1, &m2, &a2, &wh2);
+        if (!(m2 > COVER_EPS)) {
+            v[0] = w[0];
+            v[1] = w[1];
+            v[2] = w[2];
+        }
+    }
+}
+
+// The balls of the search after the first cover test: the listed balls that
+// meet the sphere when they all fit in cl (positions into cl, the extra ball
+// after them), else B itself.
+__device__ inline Balls search_balls(const Balls &B, int32_t *cl, int ncl, int ccap, int ecap) {
+    if (ncl > ccap) return B;
+    Balls C = B;
+    C.N = ncl;
+    C.idx = nullptr;
+    C.idx32 = cl;
+    C.skip = -1;
+    C.lb = INFINITY;
+    C.has_extra = B.has_extra && ecap;
+    return C;
+}
+
+__device__ inline int exist_fallback(const Balls &B, const double *o, double r, int32_t *cl, int ccap, bool compact,
+                                     double *x, unsigned long long *walks);
+
 // lazy_exist after its first cover test at direction vh: margin mx at ball
 // arg (position argpos in the list), whole-sphere holder found, the ncl balls
 // meeting the sphere listed in cl (when ncl <= ccap), the extra ball meets it
@@ -544,24 +614,14 @@ __device__ inline int lazy_exist_rest(const Balls &B0, const double *o, double r
                                       int64_t *kid, int32_t *cl, int ccap, double *x, unsigned long long *walks,
                                       double mx, int64_t arg, int whole, int ncl, int ecap, int64_t argpos) {
     const int lane = threadIdx.x & 63;
-    Balls B = B0;
     if (whole) return ST_NONE;
     if (!(mx > COVER_EPS)) {
         for (int j = 0; j < 3; ++j) x[j] = o[j] + r * vh[j];
         return ST_FOUND;
     }
     const bool compact = ncl <= ccap;
-    if (compact) {
-        Balls C = B;
-        C.N = ncl;
-        C.idx = nullptr;
-        C.idx32 = cl;
-        C.skip = -1;
-        C.lb = INFINITY;
-        C.has_extra = B.has_extra && ecap;
-        B = C;
-        arg = argpos;
-    }
+    const Balls B = search_balls(B0, cl, ncl, ccap, ecap);
+    if (compact) arg = argpos;
     int k = 0;
     if (lane == 0) {
         kid[0] = arg;
@@ -570,25 +630,11 @@ __device__ inline int lazy_exist_rest(const Balls &B0, const double *o, double r
     k = 1;
     wave_sync_lds();
     for (int round = 0; round < (B.walk_only ? 0 : 4 * KMAX); ++round) {
-        // 1. uncovered gap midpoints w.r.t. the working subset: each lane walks
-        //    rims lane and lane + 64 of the subset and keeps the first hit
-        const SubsetCaps sub{kp, k};
-        int found = 0, numeric = 0, frim = -1;
-        double mxp = 0.0, myp = 0.0;
+        // 1. uncovered gap midpoints w.r.t. the working subset
+        int found, numeric, frim;
+        double mxp, myp;
         Rim R;
-        for (int e = lane; e < k && !found; e += 64) {
-            make_rim(kp[e], R);
-            double px, py;
-            int mv;
-            const int st = rim_walk(R, sub, e, 1.0, 0.0, 1, k + 4, &px, &py, &mv);
-            if (st == 1) {
-                found = 1;
-                frim = e;
-                gap_mid(R, kp, k, e, px, py, &mxp, &myp);
-            } else if (st == 2) {
-                numeric = 1;
-            }
-        }
+        subset_gap(kp, k, found, numeric, frim, R, mxp, myp);
         if (!wor(found)) {
             if (wor(numeric)) break;  // no proof of coverage: fall back
             return ST_NONE;           // the subset covers the sphere
@@ -608,26 +654,7 @@ __device__ inline int lazy_exist_rest(const Balls &B0, const double *o, double r
             wave_cover(B, o, r, v, self, &mx, &arg, &whole);
             if (!(mx > COVER_EPS)) {
                 // verified; try to move it off the rim of `self`
-                const double uv = dot3(kp[rim_cl].u, v);
-                const double tg[3] = {kp[rim_cl].u[0] - uv * v[0], kp[rim_cl].u[1] - uv * v[1],
-                                      kp[rim_cl].u[2] - uv * v[2]};
-                const double tn = sqrt(dot3(tg, tg));
-                if (tn > 0.0) {
-                    double w[3] = {v[0] - NUDGE * tg[0] / tn, v[1] - NUDGE * tg[1] / tn, v[2] - NUDGE * tg[2] / tn};
-                    const double wn = sqrt(dot3(w, w));
-                    w[0] /= wn;
-                    w[1] /= wn;
-                    w[2] /= wn;
-                    double m2;
-                    int64_t a2;
-                    int wh2;
-                    wave_cover(B, o, r, w, -1, &m2, &a2, &wh2);
-                    if (!(m2 > COVER_EPS)) {
-                        v[0] = w[0];
-                        v[1] = w[1];
-                        v[2] = w[2];
-                    }
-                }
+                nudge_off_rim(B, o, r, kp[rim_cl], v);
                 for (int j = 0; j < 3; ++j) x[j] = o[j] + r * v[j];
                 return ST_FOUND;
             }
@@ -647,6 +674,13 @@ __device__ inline int lazy_exist_rest(const Balls &B0, const double *o, double r
         wave_sync_lds();
         if (added == 0) break;  // subset full or no progress: fall back
     }
+    return exist_fallback(B, o, r, cl, ccap, compact, x, walks);
+}
+
+// The last resort of the existence search (one wave).
+__device__ inline int exist_fallback(const Balls &B, const double *o, double r, int32_t *cl, int ccap, bool compact,
+                                     double *x, unsigned long long *walks) {
+    const int lane = threadIdx.x & 63;
     // Fallback: walk every rim of every cap (lanes over rims) against the
     // listed caps.  Its cost grows with the cube of the cap count, so it is
     // bounded by the list's size ccap: beyond it the search reports a numeric
