@@ -104,11 +104,15 @@ typedef struct {
                               batched launch has more instances than resident
                               512-thread work-groups */
     uint32_t flags;        /* SDFI_OPT_* */
-    int32_t groups;        /* work-groups that share one instance of sdfi_greedy_interpolate
-                              (its minimum-radius and re-validation searches are spread
-                              over them; a cooperative launch), 0 = 16; capped at the
-                              groups the device keeps resident; 1 = one group.  Batched
-                              launches run one group per instance. */
+    int32_t groups;        /* work-groups that share one greedy instance (a team: its
+                              minimum-radius and re-validation searches are spread over
+                              them; a cooperative launch), at most this many per
+                              instance; 0 = 16; 1 = one group per instance.  A single
+                              instance gets them all (capped at the groups the device
+                              keeps resident); a batch shares the resident groups out
+                              in proportion to each instance's pair count when there
+                              are at least two per instance, else runs one group per
+                              instance. */
 } sdfi_options;
 
 typedef struct {
@@ -132,7 +136,8 @@ typedef enum {
     SDFI_OP_GREEDY = 4,
     SDFI_OP_RMIN = 5,
     SDFI_OP_REPAIR = 6,
-    SDFI_OP_BACKWARD = 7
+    SDFI_OP_BACKWARD = 7,
+    SDFI_OP_GREEDY_INSTANCE = 8  /* bytes each instance of a batched launch adds (n, m ignored) */
 } sdfi_op;
 
 /* Fill `opt` with the defaults above. */
@@ -169,7 +174,9 @@ sdfi_status sdfi_counter_query(const char *name, int64_t *value);
 void sdfi_timing_reset(void);
 
 /* Workspace bytes that entry point `op` needs for n samples and m queries
- * (for SDFI_OP_CERTIFY n is the set size and m is ignored). */
+ * (for SDFI_OP_CERTIFY n is the set size and m is ignored).  A batched greedy
+ * launch of B instances needs SDFI_OP_GREEDY with n = total samples + B and
+ * m = total queries, plus B times SDFI_OP_GREEDY_INSTANCE. */
 sdfi_status sdfi_workspace_size(sdfi_op op, int64_t n, int64_t m, const sdfi_options *opt, size_t *bytes);
 
 /* Pairwise consistency bounds of every query (Sec. 4.3, "Further performance

@@ -219,6 +219,7 @@ sdfi_status sdfi_workspace_size(sdfi_op op, int64_t n, int64_t m, const sdfi_opt
     case SDFI_OP_RMIN: *bytes = rmin_ws(n, m, o); break;
     case SDFI_OP_REPAIR: *bytes = repair_ws(n, m, o); break;
     case SDFI_OP_BACKWARD: *bytes = backward_ws(n, m); break;
+    case SDFI_OP_GREEDY_INSTANCE: *bytes = greedy_instance_ws(o); break;
     default: set_error("unknown op %d", (int)op); return SDFI_ERR_INVALID_ARGUMENT;
     }
     return SDFI_OK;

@@ -2,8 +2,6 @@
 // minimum valid radius used by the greedy fallback and by the repair.
 #pragma once
 
-#include <hip/hip_cooperative_groups.h>
-
 #include "geom_dev.h"
 
 namespace sdfi {
@@ -73,11 +71,12 @@ struct Shared {
     int gctl, gend, gfin;  // state after the walks, at the round's end, after the fallback
 };
 
-// Several work-groups on one instance (a cooperative launch): group 0 runs
-// the greedy and posts the steps whose work is many independent sphere
-// searches (the minimum-radius candidate pulls, the re-validations) as jobs
-// on a board in global memory; every group takes items of a job from the
-// shared counter.  Grid-wide barriers open and close each job.
+// Several work-groups on one instance (a team; all groups of a cooperative
+// launch are resident at once): the team's first group runs the greedy and
+// posts the steps whose work is many independent sphere searches (the
+// minimum-radius candidate pulls, the re-validations) as jobs on a board in
+// global memory; every group of the team takes items of a job from the
+// shared counter.  A barrier of the team's groups opens and closes each job.
 enum { J_RMIN = 1, J_REVAL = 2, J_EXIT = 3 };
 
 struct Job {
@@ -93,6 +92,10 @@ struct Job {
     // the holder ring of the minimum-radius searches, shared by the team
     int64_t hring[geom::NHOLD];
     int hnext;
+    // the team's barrier: arrivals, generation; abort = a barrier waited past
+    // its bound (the run is then reported as failed)
+    unsigned bar_count, bar_gen;
+    int abort;
 };
 
 // one group's best minimum-radius answer of a pass
@@ -104,11 +107,44 @@ struct GroupBest {
 
 struct Team {
     Job *job;
-    GroupBest *best;  // one slot per group
-    int groups;
+    GroupBest *best;  // one slot per group of the team
+    int groups;       // groups in the team (1: none)
+    int first;        // the launch's block index of the team's first group
 };
 
-__device__ inline void team_sync() { cooperative_groups::this_grid().sync(); }
+// this group's rank in its team (0: the group that runs the greedy)
+__device__ inline int team_rank(const Team &T) { return (int)blockIdx.x - T.first; }
+
+// Barrier of the team's groups (every thread of each group calls it).  Each
+// wave publishes its stores device-wide first; the last group to arrive
+// starts the next generation.  A wait past 2^26 polls (about a minute) sets
+// J->abort and returns, and later barriers of the team return at once, so
+// every wave still reaches the kernel's end.
+__device__ inline void team_sync(const Team &T) {
+    Job *J = T.job;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0 && !__hip_atomic_load(&J->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        const unsigned gen = __hip_atomic_load(&J->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (atomicAdd(&J->bar_count, 1u) == (unsigned)T.groups - 1u) {
+            __hip_atomic_store(&J->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();
+            atomicAdd(&J->bar_gen, 1u);
+        } else {
+            for (uint64_t spin = 0;; ++spin) {
+                if (__hip_atomic_load(&J->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != gen) break;
+                if (__hip_atomic_load(&J->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+                if (spin > (uint64_t(1) << 26)) {
+                    __hip_atomic_store(&J->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+    }
+    __syncthreads();
+    __threadfence();
+}
 
 __device__ inline int wid() { return threadIdx.x >> 6; }
 
@@ -853,7 +889,7 @@ __device__ __noinline__ int rmin_block(const double *q, int sigma, const double 
             if (tid < geom::NHOLD) J->hring[tid] = -1;
             counter = &J->counter;
             bbits = &J->bound_bits;
-            team_sync();
+            team_sync(*team);
         }
         rmin_pull<NW>(q, p4, tie, list, len, lset, nl, deepest, Rdeep, counter, bbits, kp, kid, flist, fcap, S, prof,
                       walk_only, post ? team->job->hring : nullptr, post ? &team->job->hnext : nullptr);
@@ -861,7 +897,7 @@ __device__ __noinline__ int rmin_block(const double *q, int sigma, const double 
         GroupBest gb = group_best(S);
         if (post) {
             if (tid == 0) team->best[0] = gb;
-            team_sync();  // every group has stored its best
+            team_sync(*team);  // every group has stored its best
             for (int g = 1; g < team->groups; ++g) merge_best(gb, team->best[g]);
         }
         int res = -1;

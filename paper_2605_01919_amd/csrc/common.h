@@ -88,6 +88,7 @@ size_t bounds_ws(int64_t n, int64_t m, const sdfi_options &o);
 size_t certify_ws(int64_t N, const sdfi_options &o);
 size_t order_ws(int64_t n, int64_t m, const sdfi_options &o);
 size_t witness_ws(int64_t n, const sdfi_options &o);
+size_t greedy_instance_ws(const sdfi_options &o);
 size_t greedy_ws(int64_t n, int64_t m, const sdfi_options &o);
 size_t rmin_ws(int64_t n, int64_t m, const sdfi_options &o);
 size_t repair_ws(int64_t n, int64_t m, const sdfi_options &o);

@@ -78,7 +78,7 @@ struct GInst {
 // of fcap entries per group), and this wave's own
 template <int NW>
 __device__ inline int32_t *group_flist(const GInst &I) {
-    const int g = I.team.groups > 1 ? (int)blockIdx.x : 0;
+    const int g = I.team.groups > 1 ? blk::team_rank(I.team) : 0;
     return I.flist + (int64_t)g * NW * I.fcap;
 }
 template <int NW>
@@ -266,9 +266,9 @@ __device__ __noinline__ void revalidate(const GInst &I, int64_t N, const double 
             J->N = N;
             J->nthr = nthr;
         }
-        blk::team_sync();
+        blk::team_sync(I.team);
         reval_group<NW>(I, N, q, s, nthr, tol, SH, keep_going, &J->counter, &J->fail);
-        blk::team_sync();
+        blk::team_sync(I.team);
         if (threadIdx.x == 0) SH.fail = __hip_atomic_load(&J->fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else if (nthr <= NW / 4 || I.team.groups > 1) {
         reval_group<NW>(I, N, q, s, nthr, tol, SH, keep_going, &SH.counter, &SH.fail);
@@ -284,29 +284,42 @@ template <int NW>
 __device__ __noinline__ void helper_loop(const GInst &I, double tol, StepShared<NW> &SH) {
     blk::Job *J = I.team.job;
     for (;;) {
-        blk::team_sync();
+        blk::team_sync(I.team);
         const int type = __hip_atomic_load(&J->type, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (type == blk::J_EXIT) return;
+        if (type == blk::J_EXIT || __hip_atomic_load(&J->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
         if (type == blk::J_RMIN) {
             blk::rmin_pull_job<NW>(J, I.CP, I.list, SH.kp, SH.kid, group_flist<NW>(I), I.fcap, SH.S,
-                                   I.team.best + blockIdx.x, I.profile ? I.counts + C_RP0 : nullptr, I.walk_only);
+                                   I.team.best + blk::team_rank(I.team), I.profile ? I.counts + C_RP0 : nullptr,
+                                   I.walk_only);
         } else if (type == blk::J_REVAL) {
             const double q[3] = {J->q[0], J->q[1], J->q[2]};
             reval_group<NW>(I, J->N, q, J->s, J->nthr, tol, SH, J->keep_going != 0, &J->counter, &J->fail);
         }
-        blk::team_sync();
+        blk::team_sync(I.team);
     }
 }
 
 template <int NW>
 __global__ __launch_bounds__(NW * 64) void greedy_kernel(const GInst *insts, double tol, double tie, double dlo0,
                                                          double dlo1, double dlo2, double dhi0, double dhi1,
-                                                         double dhi2, int groups) {
+                                                         double dhi2, int teams) {
     constexpr int GBS = NW * 64;
     __shared__ StepShared<NW> SH;
-    // groups > 1: all groups of the launch work on instance 0 (a team)
-    const GInst I = insts[groups > 1 ? 0 : blockIdx.x];
-    if (groups > 1 && blockIdx.x > 0) {
+    // teams > 0: a team launch of that many instances, each on the groups
+    // [team.first, team.first + team.groups); else one group per instance
+    int ii = blockIdx.x;
+    if (teams > 0) {
+        int lo = 0, hi = teams - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (insts[mid].team.first <= (int)blockIdx.x) lo = mid;
+            else hi = mid - 1;
+        }
+        ii = lo;
+    }
+    const GInst I = insts[ii];
+    const bool team = I.team.groups > 1;
+    if (team && blk::team_rank(I.team) > 0) {
         helper_loop<NW>(I, tol, SH);
         return;
     }
@@ -469,7 +482,7 @@ __global__ __launch_bounds__(NW * 64) void greedy_kernel(const GInst *insts, dou
                         int64_t sph;
                         int kk = blk::rmin_block<NW>(q, sigma, I.CP, I.CW, N, tol, tie, I.list, SH.kp, SH.kid, I.flist,
                                                      I.fcap, SH.S, &rr, x, &sph, I.profile ? I.counts + C_RP0 : nullptr,
-                                                     I.walk_only, groups > 1 ? &I.team : nullptr);
+                                                     I.walk_only, team ? &I.team : nullptr);
                         if (kk == -2 && tid == 0) atomicAdd(&I.counts[C_NUMERIC], 1ull);
                         if (kk > 0) {
                             val = sigma * rr;
@@ -541,10 +554,10 @@ __global__ __launch_bounds__(NW * 64) void greedy_kernel(const GInst *insts, dou
         __syncthreads();
         if (tid == 0) I.counts[C_T_RECORD] += wall_clock64() - t_mark;
     }
-    if (groups > 1) {
+    if (team) {
         // release the helper groups
         if (tid == 0) __hip_atomic_store(&I.team.job->type, blk::J_EXIT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        blk::team_sync();
+        blk::team_sync(I.team);
     }
     // final witnesses of the query spheres and of the samples
     for (int64_t c = n + tid; c < N; c += GBS) {
@@ -671,7 +684,7 @@ int team_groups(const sdfi_options &o, int nw) {
     return std::max(1, std::min(team_request(o), slots));
 }
 
-// groups: work-groups per instance (a team when > 1, single instance only)
+// groups: the most work-groups any instance gets (a team when > 1)
 GBufs carve_greedy(Carver &c, int64_t n, int64_t m, int ninst, int nw, int groups) {
     GBufs b;
     int64_t cap = n + m + 1;
@@ -687,14 +700,22 @@ GBufs carve_greedy(Carver &c, int64_t n, int64_t m, int ninst, int nw, int group
     b.order = c.take<int64_t>(m + 1);
     b.seg = c.take<int64_t>(ninst + 1);
     b.inst = c.take<GInst>(ninst);
-    b.job = c.take<blk::Job>(1);
-    b.best = c.take<blk::GroupBest>(groups);
+    b.job = c.take<blk::Job>(ninst);
+    b.best = c.take<blk::GroupBest>((int64_t)groups * ninst);
     return b;
 }
 
 }  // namespace
 
 size_t witness_ws(int64_t, const sdfi_options &) { return 256; }
+
+// what each further instance of a batched launch takes: counters, its
+// descriptor, offsets, job board and group slots (with the alignment of
+// each carved array)
+size_t greedy_instance_ws(const sdfi_options &o) {
+    return sizeof(unsigned long long) * C_NCOUNT + sizeof(GInst) + sizeof(int64_t) + sizeof(blk::Job) +
+           sizeof(blk::GroupBest) * (size_t)team_request(o) + 2 * sizeof(int64_t);
+}
 
 sdfi_status run_witnesses(const double *samples, int64_t n, double *w, uint8_t *st, const sdfi_options &o,
                           hipStream_t s, const int64_t *seg, int nseg) {
@@ -709,7 +730,7 @@ sdfi_status run_witnesses(const double *samples, int64_t n, double *w, uint8_t *
 
 size_t greedy_ws(int64_t n, int64_t m, const sdfi_options &o) {
     Carver c(nullptr, 0, true);
-    carve_greedy(c, n, m, 1, greedy_waves(o), team_request(o));
+    carve_greedy(c, n + 1, m, 1, greedy_waves(o), team_request(o));  // as greedy_common carves one instance
     Carver c2(nullptr, 0, true);
     size_t ord = order_ws(n, m, o);
     size_t cert = (o.flags & SDFI_OPT_CERTIFY) ? certify_ws(n + m, o) + 4 * (n + m) * 8 + 3 * (n + m) * 8 + 1024 : 0;
@@ -724,6 +745,11 @@ sdfi_status run_order_batched(int ninst, const int64_t *soff, const int32_t *gri
 
 static double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+__global__ void zero_words_kernel(unsigned *p, int64_t k) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < k) p[i] = 0u;
 }
 
 __global__ void pack_set_kernel(const double *samples, int64_t n, const double *queries, const double *values,
@@ -764,8 +790,42 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
     const int64_t n = soff[ninst], m = qoff[ninst];
     Carver c(ws, ws_bytes);
     const int nw = greedy_waves(o, ninst);
-    const int groups = ninst == 1 ? team_groups(o, nw) : 1;
-    GBufs b = carve_greedy(c, n + ninst, m, ninst, nw, groups);
+    // work-groups per instance: a team when more than one (all resident: a
+    // cooperative launch); a batch shares the resident groups out by pair
+    // count when there are at least two per instance
+    std::vector<int> G(ninst, 1);
+    {
+        const int slots = resident_groups(nw);
+        const int cap = team_request(o);
+        if (ninst == 1) {
+            G[0] = team_groups(o, nw);
+        } else if (cap > 1 && slots >= 2 * ninst) {
+            const int total = std::min<int64_t>(slots, (int64_t)cap * ninst);
+            double wsum = 0.0;
+            std::vector<double> wk(ninst);
+            for (int i = 0; i < ninst; ++i) {
+                const double ni = (double)(soff[i + 1] - soff[i]), mi = (double)(qoff[i + 1] - qoff[i]);
+                wk[i] = ni * mi + 0.5 * mi * mi;
+                wsum += wk[i];
+            }
+            int used = 0;
+            for (int i = 0; i < ninst; ++i) {
+                G[i] = std::max(1, std::min(cap, (int)(total * (wsum > 0.0 ? wk[i] / wsum : 1.0 / ninst))));
+                used += G[i];
+            }
+            while (used > total) {  // trim the largest teams
+                int big = 0;
+                for (int i = 1; i < ninst; ++i)
+                    if (G[i] > G[big]) big = i;
+                if (G[big] <= 1) break;
+                --G[big];
+                --used;
+            }
+        }
+    }
+    const int gmax = *std::max_element(G.begin(), G.end());
+    const bool teams = gmax > 1;
+    GBufs b = carve_greedy(c, n + ninst, m, ninst, nw, team_request(o));
     if (!c.ok()) {
         set_error("workspace too small for the greedy interpolation");
         return SDFI_ERR_WORKSPACE;
@@ -874,13 +934,14 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
         // each wave's cap list holds every ball of a small instance, FALLBACK_GLOBAL otherwise
         g.fcap = (int)std::min<int64_t>(geom::FALLBACK_GLOBAL, ni + mi + 1);
         g.flist = b.flist + fpos;
-        fpos += (int64_t)nw * g.fcap;
+        fpos += (int64_t)G[i] * nw * g.fcap;
         g.counts = b.counts + C_NCOUNT * i;
         g.profile = timing_enabled() ? 1 : 0;
         g.walk_only = (o.flags & SDFI_OPT_EXHAUSTIVE) ? 1 : 0;
-        g.team.job = b.job;
-        g.team.best = b.best;
-        g.team.groups = groups;
+        g.team.job = b.job + i;
+        g.team.best = b.best + (int64_t)team_request(o) * i;
+        g.team.groups = G[i];
+        g.team.first = 0;  // set below, in launch order
         g.n = ni;
         g.m = mi;
         cpos += ni + mi;
@@ -891,31 +952,48 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
     std::stable_sort(hi.begin(), hi.end(), [](const GInst &x, const GInst &y) {
         return x.n * x.m + x.m * x.m / 2 > y.n * y.m + y.m * y.m / 2;
     });
+    // teams take consecutive blocks in launch order
+    int nblocks = 0;
+    for (int k = 0; k < ninst; ++k) {
+        hi[k].team.first = nblocks;
+        nblocks += hi[k].team.groups;
+    }
     SDFI_HIP(hipMemcpyAsync(b.inst, hi.data(), sizeof(GInst) * ninst, hipMemcpyHostToDevice, st));
+    if (teams) {
+        const int64_t words = (int64_t)(sizeof(blk::Job) * ninst / sizeof(unsigned));
+        zero_words_kernel<<<(unsigned)((words + 255) / 256), 256, 0, st>>>(reinterpret_cast<unsigned *>(b.job), words);
+    }
     KernelTimer tm("greedy", st);
-    if (groups > 1) {
-        // one instance, `groups` work-groups: a cooperative launch (all resident)
+    if (teams) {
+        // every group resident at once: a cooperative launch
         const GInst *ip = b.inst;
         double tol = o.tol, tie = o.tie_tol;
         double d0 = o.domain_lo[0], d1 = o.domain_lo[1], d2 = o.domain_lo[2];
         double d3 = o.domain_hi[0], d4 = o.domain_hi[1], d5 = o.domain_hi[2];
-        int gr = groups;
-        void *args[] = {&ip, &tol, &tie, &d0, &d1, &d2, &d3, &d4, &d5, &gr};
+        int nt = ninst;
+        void *args[] = {&ip, &tol, &tie, &d0, &d1, &d2, &d3, &d4, &d5, &nt};
         const void *fn = nw == 4 ? (const void *)greedy_kernel<4> : (const void *)greedy_kernel<NW_DEFAULT>;
-        SDFI_HIP(hipLaunchCooperativeKernel(fn, dim3(groups), dim3(nw * 64), args, 0, st));
+        SDFI_HIP(hipLaunchCooperativeKernel(fn, dim3(nblocks), dim3(nw * 64), args, 0, st));
     } else if (nw == 4) {
         greedy_kernel<4><<<ninst, 4 * 64, 0, st>>>(b.inst, o.tol, o.tie_tol, o.domain_lo[0], o.domain_lo[1],
-                                                   o.domain_lo[2], o.domain_hi[0], o.domain_hi[1], o.domain_hi[2], 1);
+                                                   o.domain_lo[2], o.domain_hi[0], o.domain_hi[1], o.domain_hi[2], 0);
     } else {
         greedy_kernel<NW_DEFAULT><<<ninst, NW_DEFAULT * 64, 0, st>>>(b.inst, o.tol, o.tie_tol, o.domain_lo[0],
                                                                      o.domain_lo[1], o.domain_lo[2], o.domain_hi[0],
-                                                                     o.domain_hi[1], o.domain_hi[2], 1);
+                                                                     o.domain_hi[1], o.domain_hi[2], 0);
     }
     tm.stop();
     SDFI_HIP(hipGetLastError());
     std::vector<unsigned long long> cnt(C_NCOUNT * ninst);
     SDFI_HIP(hipMemcpyAsync(cnt.data(), b.counts, sizeof(unsigned long long) * cnt.size(), hipMemcpyDeviceToHost, st));
+    std::vector<blk::Job> jobs(teams ? ninst : 0);
+    if (teams) SDFI_HIP(hipMemcpyAsync(jobs.data(), b.job, sizeof(blk::Job) * ninst, hipMemcpyDeviceToHost, st));
     SDFI_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < (int)jobs.size(); ++i)
+        if (jobs[i].abort) {
+            set_error("instance %d: a barrier of its work-groups waited past its bound; the results are not valid", i);
+            return SDFI_ERR_DEVICE;
+        }
     double t3 = now_ms();
     if (report) {
         std::memset(report, 0, sizeof(*report));
@@ -1049,7 +1127,7 @@ extern "C" sdfi_status sdfi_greedy_interpolate_batched(int32_t num_instances, co
     const int64_t n = sample_offsets[num_instances], m = query_offsets[num_instances];
     SDFI_CHECK_ARG(n + m < (int64_t(1) << 31), "total size out of range");
     SDFI_CHECK_ARG(samples && queries && values && order_out && active && kind && witness, "null array argument");
-    size_t need = greedy_ws(n + num_instances, m, o);
+    size_t need = greedy_ws(n + num_instances, m, o) + (size_t)num_instances * greedy_instance_ws(o);
     if (ws_bytes < need || !ws) {
         set_error("workspace of %zu bytes is below the %zu required", ws_bytes, need);
         return SDFI_ERR_WORKSPACE;

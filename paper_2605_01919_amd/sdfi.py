@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libsdfi.so")
 PREC_FP64 = 0
 PREC_FP32_FP64_RECHECK = 1
 
-OP_BOUNDS, OP_CERTIFY, OP_ORDER, OP_WITNESS, OP_GREEDY, OP_RMIN, OP_REPAIR, OP_BACKWARD = range(8)
+OP_BOUNDS, OP_CERTIFY, OP_ORDER, OP_WITNESS, OP_GREEDY, OP_RMIN, OP_REPAIR, OP_BACKWARD, OP_GREEDY_INSTANCE = range(9)
 
 KIND_KEPT, KIND_HI, KIND_LO, KIND_ZERO, KIND_RMIN_T, KIND_RMIN_D, KIND_RMIN_U, KIND_COINCIDENT = range(8)
 KIND_INFEASIBLE, KIND_UNRESOLVED = 254, 255
@@ -144,10 +144,14 @@ def counter_read(name):
     return v.value
 
 
-def workspace(op, n, m, opt):
+def workspace_bytes(op, n, m, opt):
     size = ctypes.c_size_t()
     _check(lib().sdfi_workspace_size(op, n, m, ctypes.byref(opt), ctypes.byref(size)), "sdfi_workspace_size")
-    return torch.empty(max(int(size.value), 256), dtype=torch.uint8, device="cuda")
+    return int(size.value)
+
+
+def workspace(op, n, m, opt, extra=0):
+    return torch.empty(max(workspace_bytes(op, n, m, opt) + extra, 256), dtype=torch.uint8, device="cuda")
 
 
 def bounds(samples, queries, precision="fp32"):
@@ -262,7 +266,7 @@ def greedy(samples, queries, order=None, grid=0, certify=False, input_check=Fals
     return out
 
 
-def greedy_batched(instances, certify=False, block_size=0):
+def greedy_batched(instances, certify=False, block_size=0, groups=0):
     """instances: list of (samples (n_i,4), queries (8 n_i,3), grid_i) GPU tensors."""
     soff = [0]
     qoff = [0]
@@ -275,7 +279,7 @@ def greedy_batched(instances, certify=False, block_size=0):
     so = (ctypes.c_int64 * len(soff))(*soff)
     qo = (ctypes.c_int64 * len(qoff))(*qoff)
     n, m = soff[-1], qoff[-1]
-    opt = options(flags=OPT_CERTIFY if certify else 0, block_size=block_size)
+    opt = options(flags=OPT_CERTIFY if certify else 0, block_size=block_size, groups=groups)
     dev = samples.device
     out = {
         "values": torch.empty(m, dtype=torch.float64, device=dev),
@@ -286,7 +290,8 @@ def greedy_batched(instances, certify=False, block_size=0):
         "sample_offsets": soff, "query_offsets": qoff,
     }
     rep = Report()
-    ws = workspace(OP_GREEDY, n + len(instances), m, opt)
+    ws = workspace(OP_GREEDY, n + len(instances), m, opt,
+                   extra=len(instances) * workspace_bytes(OP_GREEDY_INSTANCE, 0, 0, opt))
     _check(lib().sdfi_greedy_interpolate_batched(
         ctypes.c_int32(len(instances)), so, qo, grids, _ptr(samples), _ptr(queries), _ptr(out["values"]),
         _ptr(out["order"]), _ptr(out["active"]), _ptr(out["kind"]), _ptr(out["witness"]), ctypes.byref(rep),
