@@ -42,6 +42,7 @@ struct Shared {
     double rv[NW][RAYMAX];
     int64_t ri[NW];
     int cnt[NW];
+    int cnt2[NW];
     int counter;
     // minimum valid radius result slots, one per wave
     double wd[NW];
@@ -416,6 +417,57 @@ __device__ inline int bor(int v, Shared<NW> &S) {
 
 // Append flagged items of one chunk (item base + threadIdx.x) to out[], in
 // index order; returns the new length.  All threads call it.
+// Ordered compaction of the rows c of [0, N) for which pred(c, f1, f2) sets
+// f1 (into out1) or f2 (into out2), each list in row order, without a
+// barrier per row block: wave w takes the contiguous slice w of the rows and
+// stages its items in stage[w * scap ...] (first list from the front, second
+// from the middle), then the slices' lists are concatenated.  Returns false,
+// having written nothing, when a slice does not fit (2 x slice > scap).
+template <int NW, class Pred>
+__device__ bool bcompact2(int64_t N, Pred pred, int64_t *out1, int64_t cap1, int64_t *len1, int64_t *out2,
+                          int64_t cap2, int64_t *len2, int32_t *stage, int scap, Shared<NW> &S) {
+    const int64_t chunk = ((N + NW - 1) / NW + 63) / 64 * 64;
+    if (2 * chunk > scap) return false;  // uniform
+    const int w = wid(), ln = lane();
+    const int64_t fb = min(N, (int64_t)w * chunk), fe = min(N, fb + chunk);
+    int32_t *st1 = stage + (int64_t)w * scap, *st2 = st1 + chunk;
+    int c1 = 0, c2 = 0;
+    const unsigned long long below = (1ull << ln) - 1ull;
+    for (int64_t f0 = fb; f0 < fe; f0 += 64) {
+        const int64_t c = f0 + ln;
+        bool f1 = false, f2 = false;
+        if (c < fe) pred(c, f1, f2);
+        const unsigned long long m1 = __ballot(f1), m2 = __ballot(f2);
+        if (f1) st1[c1 + __popcll(m1 & below)] = (int32_t)c;
+        if (f2) st2[c2 + __popcll(m2 & below)] = (int32_t)c;
+        c1 += __popcll(m1);
+        c2 += __popcll(m2);
+    }
+    if (ln == 0) {
+        S.cnt[w] = c1;
+        S.cnt2[w] = c2;
+    }
+    __threadfence_block();
+    __syncthreads();
+    int64_t o1 = 0, o2 = 0, t1 = 0, t2 = 0;
+    for (int v = 0; v < NW; ++v) {
+        if (v < w) {
+            o1 += S.cnt[v];
+            o2 += S.cnt2[v];
+        }
+        t1 += S.cnt[v];
+        t2 += S.cnt2[v];
+    }
+    for (int k = ln; k < c1; k += 64)
+        if (o1 + k < cap1) out1[o1 + k] = st1[k];
+    for (int k = ln; k < c2; k += 64)
+        if (o2 + k < cap2) out2[o2 + k] = st2[k];
+    __syncthreads();
+    *len1 = t1;
+    *len2 = t2;
+    return true;
+}
+
 template <int NW>
 __device__ inline int64_t bappend(bool flag, int64_t item, int64_t len, int64_t *out, int64_t cap, Shared<NW> &S) {
     unsigned long long m = __ballot(flag);
@@ -837,19 +889,22 @@ __device__ __noinline__ int rmin_block(const double *q, int sigma, const double 
         // within `bound` of q (deepest first): a sphere's uncovered points lie
         // outside every other ball, the deepest one included
         int64_t len = 0, nl = 0;
-        for (int64_t base = 0; base < N; base += BS) {
-            int64_t c = base + tid;
-            bool f = false, inl = false;
-            if (c < N) {
-                const double *p = p4 + 4 * c;
-                double d = geom::dist3(q, p);
-                if (c != deepest && sign_class(p[3], tie) == sigma && fabs(d - fabs(p[3])) <= bound)
-                    f = dist_outside_ball(q, p, fabs(p[3]), pdeep, Rdeep) <= bound;
-                // the local set: balls that can cover a point within `bound` of q
-                inl = isinf(bound) || d < fabs(p[3]) + bound;
+        auto select = [&](int64_t c, bool &f, bool &inl) {
+            const double *p = p4 + 4 * c;
+            double d = geom::dist3(q, p);
+            if (c != deepest && sign_class(p[3], tie) == sigma && fabs(d - fabs(p[3])) <= bound)
+                f = dist_outside_ball(q, p, fabs(p[3]), pdeep, Rdeep) <= bound;
+            // the local set: balls that can cover a point within `bound` of q
+            inl = isinf(bound) || d < fabs(p[3]) + bound;
+        };
+        if (!bcompact2<NW>(N, select, list + 1, N, &len, lset, N, &nl, flist, fcap, S)) {
+            for (int64_t base = 0; base < N; base += BS) {
+                int64_t c = base + tid;
+                bool f = false, inl = false;
+                if (c < N) select(c, f, inl);
+                len = bappend(f, c, len, list + 1, N, S);
+                nl = bappend(inl, c, nl, lset, N, S);
             }
-            len = bappend(f, c, len, list + 1, N, S);
-            nl = bappend(inl, c, nl, lset, N, S);
         }
         if (tid == 0) list[0] = deepest;
         ++len;

@@ -111,10 +111,15 @@ __device__ int64_t threatened(const GInst &I, int64_t N, const double *q, double
     constexpr int GBS = NW * 64;
     int64_t cnt = 0;
     if (rn > 0.0) {
-        for (int64_t base = 0; base < N; base += GBS) {
-            int64_t c = base + threadIdx.x;
-            bool f = c < N && geom::dist3(I.CW + 3 * c, q) < rn;
-            cnt = blk::bappend(f, c, cnt, I.list, n + m + 1, SH.S);
+        auto select = [&](int64_t c, bool &f, bool &) { f = geom::dist3(I.CW + 3 * c, q) < rn; };
+        int64_t none = 0;
+        if (!blk::bcompact2<NW>(N, select, I.list, n + m + 1, &cnt, I.list, 0, &none, group_flist<NW>(I), I.fcap,
+                                SH.S)) {
+            for (int64_t base = 0; base < N; base += GBS) {
+                int64_t c = base + threadIdx.x;
+                bool f = c < N && geom::dist3(I.CW + 3 * c, q) < rn;
+                cnt = blk::bappend(f, c, cnt, I.list, n + m + 1, SH.S);
+            }
         }
     }
     return cnt > n + m ? n + m : cnt;
