@@ -527,9 +527,26 @@ __device__ inline double dist_outside_ball(const double *q, const double *p, dou
 // registers.  All threads of the work-group call it.
 template <int NW>
 __device__ __noinline__ double ray_bound(const double *q, int sigma, const double *p4, int64_t N, double tie,
-                                         int64_t deepest, double depth, double known, Shared<NW> &S) {
+                                         int64_t deepest, double depth, double known, Shared<NW> &S,
+                                         int64_t *rows, int32_t *stage, int scap) {
     const int tid = threadIdx.x;
     const int BS = NW * 64;
+    // A ray stops at `known` (an upper bound of the answer already): only
+    // balls that can hold a ray point nearer than that take part, listed
+    // first in rows[] (all sigma balls when `known` is unbounded or the list
+    // does not fit its staging).
+    int64_t nr = N;
+    const int64_t *idx = nullptr;
+    if (known < INFINITY) {
+        auto near = [&](int64_t c, bool &f, bool &) {
+            const double *p = p4 + 4 * c;
+            const double R = fabs(p[3]) - tie;
+            f = sign_class(p[3], tie) == sigma && R > 0.0 && geom::dist3(q, p) < R + known;
+        };
+        int64_t none = 0;
+        if (bcompact2<NW>(N, near, rows, N, &nr, rows, 0, &none, stage, scap, S)) idx = rows;
+        else nr = N;
+    }
     {
         double dir[NRAY][3];
         {
@@ -564,8 +581,8 @@ __device__ __noinline__ double ray_bound(const double *q, int sigma, const doubl
             if (widened && ++wide_steps > 6) break;
             double step[NRAY];
             for (int k = 0; k < NRAY; ++k) step[k] = 0.0;
-            for (int64_t c = tid; c < N; c += BS) {
-                const double *p = p4 + 4 * c;
+            for (int64_t c = tid; c < nr; c += BS) {
+                const double *p = p4 + 4 * (idx ? idx[c] : c);
                 if (sign_class(p[3], tie) != sigma) continue;
                 const double R = fabs(p[3]) - tie;
                 if (!(R > 0.0)) continue;
@@ -590,7 +607,7 @@ __device__ __noinline__ double ray_bound(const double *q, int sigma, const doubl
                 }
             }
             for (int k = 0; k < NRAY; ++k)
-                if (((live >> k) & 1u) && !(t[k] < nearest)) live &= ~(1u << k);
+                if (((live >> k) & 1u) && !(t[k] < fmin(nearest, known))) live &= ~(1u << k);
         }
         // the exit may lie in a tol-thin overlap with an opposite-sign ball,
         // whose uncovered edge is within sqrt(2 R tol) of it: a margin of 2e-3
@@ -870,7 +887,7 @@ __device__ __noinline__ int rmin_block(const double *q, int sigma, const double 
     // it; the first point no ball holds is off the union, so the contour is no
     // farther from q than that point.  The rays advance together, one block
     // scan per step; a ray stops once it is past the nearest exit found.
-    rbound = ray_bound<NW>(q, sigma, p4, N, tie, deepest, depth, wbound, S);
+    rbound = ray_bound<NW>(q, sigma, p4, N, tie, deepest, depth, wbound, S, list, flist, fcap);
     bound = fmin(bound, rbound);
     lap(RP_T_RAY);
     int64_t *lset = list + (N + 1);
