@@ -423,9 +423,12 @@ __device__ inline int bor(int v, Shared<NW> &S) {
 // stages its items in stage[w * scap ...] (first list from the front, second
 // from the middle), then the slices' lists are concatenated.  Returns false,
 // having written nothing, when a slice does not fit (2 x slice > scap).
+// With `map`, position c stands for row map[c] (an index list in row order),
+// which is what the lists receive.
 template <int NW, class Pred>
 __device__ bool bcompact2(int64_t N, Pred pred, int64_t *out1, int64_t cap1, int64_t *len1, int64_t *out2,
-                          int64_t cap2, int64_t *len2, int32_t *stage, int scap, Shared<NW> &S) {
+                          int64_t cap2, int64_t *len2, int32_t *stage, int scap, Shared<NW> &S,
+                          const int64_t *map = nullptr) {
     const int64_t chunk = ((N + NW - 1) / NW + 63) / 64 * 64;
     if (2 * chunk > scap) return false;  // uniform
     const int w = wid(), ln = lane();
@@ -434,9 +437,10 @@ __device__ bool bcompact2(int64_t N, Pred pred, int64_t *out1, int64_t cap1, int
     int c1 = 0, c2 = 0;
     const unsigned long long below = (1ull << ln) - 1ull;
     for (int64_t f0 = fb; f0 < fe; f0 += 64) {
-        const int64_t c = f0 + ln;
+        const int64_t j = f0 + ln;
+        const int64_t c = j < fe && map ? map[j] : j;
         bool f1 = false, f2 = false;
-        if (c < fe) pred(c, f1, f2);
+        if (j < fe) pred(c, f1, f2);
         const unsigned long long m1 = __ballot(f1), m2 = __ballot(f2);
         if (f1) st1[c1 + __popcll(m1 & below)] = (int32_t)c;
         if (f2) st2[c2 + __popcll(m2 & below)] = (int32_t)c;
@@ -528,25 +532,13 @@ __device__ inline double dist_outside_ball(const double *q, const double *p, dou
 template <int NW>
 __device__ __noinline__ double ray_bound(const double *q, int sigma, const double *p4, int64_t N, double tie,
                                          int64_t deepest, double depth, double known, Shared<NW> &S,
-                                         int64_t *rows, int32_t *stage, int scap) {
+                                         const int64_t *idx, int64_t nr) {
     const int tid = threadIdx.x;
     const int BS = NW * 64;
-    // A ray stops at `known` (an upper bound of the answer already): only
-    // balls that can hold a ray point nearer than that take part, listed
-    // first in rows[] (all sigma balls when `known` is unbounded or the list
-    // does not fit its staging).
-    int64_t nr = N;
-    const int64_t *idx = nullptr;
-    if (known < INFINITY) {
-        auto near = [&](int64_t c, bool &f, bool &) {
-            const double *p = p4 + 4 * c;
-            const double R = fabs(p[3]) - tie;
-            f = sign_class(p[3], tie) == sigma && R > 0.0 && geom::dist3(q, p) < R + known;
-        };
-        int64_t none = 0;
-        if (bcompact2<NW>(N, near, rows, N, &nr, rows, 0, &none, stage, scap, S)) idx = rows;
-        else nr = N;
-    }
+    // A ray stops at `known` (an upper bound of the answer already), so only
+    // balls that can hold a ray point nearer than that matter: the rows
+    // idx[0..nr) when given (a superset of those, in row order), else all N.
+    if (!idx) nr = N;
     {
         double dir[NRAY][3];
         {
@@ -835,7 +827,7 @@ __device__ __noinline__ int rmin_block(const double *q, int sigma, const double 
                                  int32_t *flist, int fcap,
                                  Shared<NW> &S, double *r_out, double *x_out, int64_t *sphere_out,
                                  unsigned long long *prof = nullptr, int walk_only = 0,
-                                 const Team *team = nullptr) {
+                                 const Team *team = nullptr, int64_t *near = nullptr) {
     const int tid = threadIdx.x;
     const int BS = NW * 64;
     unsigned long long tmark = (prof && tid == 0) ? wall_clock64() : 0ull;
@@ -870,8 +862,25 @@ __device__ __noinline__ int rmin_block(const double *q, int sigma, const double 
     }
     depth = bmax(depth, S);
     wbest = bmin(wbest, S);
+    const double wbound = isinf(wbest) ? INFINITY : wbest * (1.0 + 1e-12) + 1e-15;
+    // The balls near q, in row order: those that can cover a point within the
+    // witness bound of q (d <= |s| + wbound).  Every ball the first pass
+    // lists, every ball a ray meets before that bound, and the deepest ball
+    // (it holds q) are among them; wider passes scan all rows.
+    int64_t nn = N;
+    const int64_t *nidx = nullptr;
+    if (near && wbound < INFINITY) {
+        auto sel = [&](int64_t c, bool &f, bool &) {
+            const double *p = p4 + 4 * c;
+            f = geom::dist3(q, p) <= fabs(p[3]) + wbound;
+        };
+        int64_t none = 0;
+        if (bcompact2<NW>(N, sel, near, N, &nn, near, 0, &none, flist, fcap, S)) nidx = near;
+        else nn = N;
+    }
     int64_t deepest = INT64_MAX;
-    for (int64_t c = tid; c < N; c += BS) {
+    for (int64_t j = tid; j < nn; j += BS) {
+        const int64_t c = nidx ? nidx[j] : j;
         const double *p = p4 + 4 * c;
         if (sign_class(p[3], tie) != sigma) continue;
         if (fabs(p[3]) - geom::dist3(q, p) == depth) deepest = deepest < c ? deepest : c;
@@ -879,7 +888,6 @@ __device__ __noinline__ int rmin_block(const double *q, int sigma, const double 
     deepest = bmin_i64(deepest, S);
     lap(RP_T_SCAN);
     if (deepest == INT64_MAX) return -2;  // no ball attains the depth (only with NaN data): no answer
-    const double wbound = isinf(wbest) ? INFINITY : wbest * (1.0 + 1e-12) + 1e-15;
     double bound = wbound, rbound = INFINITY;
     // A second upper bound: the nearest exit of NRAY rays from q (away from the
     // deepest centre, along the axes and the diagonals).  At each point of a
@@ -887,7 +895,7 @@ __device__ __noinline__ int rmin_block(const double *q, int sigma, const double 
     // it; the first point no ball holds is off the union, so the contour is no
     // farther from q than that point.  The rays advance together, one block
     // scan per step; a ray stops once it is past the nearest exit found.
-    rbound = ray_bound<NW>(q, sigma, p4, N, tie, deepest, depth, wbound, S, list, flist, fcap);
+    rbound = ray_bound<NW>(q, sigma, p4, N, tie, deepest, depth, wbound, S, nidx, nn);
     bound = fmin(bound, rbound);
     lap(RP_T_RAY);
     int64_t *lset = list + (N + 1);
@@ -914,7 +922,10 @@ __device__ __noinline__ int rmin_block(const double *q, int sigma, const double 
             // the local set: balls that can cover a point within `bound` of q
             inl = isinf(bound) || d < fabs(p[3]) + bound;
         };
-        if (!bcompact2<NW>(N, select, list + 1, N, &len, lset, N, &nl, flist, fcap, S)) {
+        // the first pass's bound is at most the witness bound: the near rows hold its lists
+        const bool from_near = nidx && bound <= wbound;
+        if (!bcompact2<NW>(from_near ? nn : N, select, list + 1, N, &len, lset, N, &nl, flist, fcap, S,
+                           from_near ? nidx : nullptr)) {
             for (int64_t base = 0; base < N; base += BS) {
                 int64_t c = base + tid;
                 bool f = false, inl = false;

@@ -66,7 +66,7 @@ struct GInst {
     int64_t *list;           // 2 (n + m + 1) scratch
     int32_t *flist;          // one cap list of fcap entries per wavefront, for the exhaustive searches
     int fcap;
-    double *pend;            // (n + m) x 3 pending witness updates
+    double *pend;            // (n + m) x 3 pending witness updates (the minimum radius's near rows meanwhile)
     unsigned long long *counts;  // C_NCOUNT
     int64_t n, m;
     int profile;             // record the finer sub-phase split (while timing is enabled)
@@ -487,7 +487,8 @@ __global__ __launch_bounds__(NW * 64) void greedy_kernel(const GInst *insts, dou
                         int64_t sph;
                         int kk = blk::rmin_block<NW>(q, sigma, I.CP, I.CW, N, tol, tie, I.list, SH.kp, SH.kid, I.flist,
                                                      I.fcap, SH.S, &rr, x, &sph, I.profile ? I.counts + C_RP0 : nullptr,
-                                                     I.walk_only, team ? &I.team : nullptr);
+                                                     I.walk_only, team ? &I.team : nullptr,
+                                                     reinterpret_cast<int64_t *>(I.pend));
                         if (kk == -2 && tid == 0) atomicAdd(&I.counts[C_NUMERIC], 1ull);
                         if (kk > 0) {
                             val = sigma * rr;

@@ -36,7 +36,7 @@ __global__ __launch_bounds__(RBS) void rmin_kernel(const double *pts, const int8
                                                    double tol, double tie, double *val, uint8_t *kind, double *wout,
                                                    int64_t *lists, int32_t *flists, int fcap) {
     __shared__ RShared SH;
-    int64_t *list = lists + (int64_t)blockIdx.x * 2 * (nb + 1);
+    int64_t *list = lists + (int64_t)blockIdx.x * 3 * (nb + 1);  // candidates, local set, near rows
     int32_t *flist = flists + (int64_t)blockIdx.x * RW * fcap;
     for (int64_t k = blockIdx.x; k < K; k += gridDim.x) {
         const double q[3] = {pts[3 * k], pts[3 * k + 1], pts[3 * k + 2]};
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(RBS) void rmin_kernel(const double *pts, const int8
         int64_t sph = -1;
         int kk = sigma == 0 ? 0
                             : blk::rmin_block<RW>(q, sigma, p4, W, nb, tol, tie, list, SH.kp, SH.kid, flist, fcap, SH.S, &r, x,
-                                                  &sph);
+                                                  &sph, nullptr, 0, nullptr, list + 2 * (nb + 1));
         if (threadIdx.x == 0) {
             bool forced = force && force[k] != 0;
             if (kk > 0) {
@@ -154,7 +154,7 @@ size_t rmin_ws(int64_t n, int64_t m, const sdfi_options &) {
     c.take<char>(check_ws(0));                    // input checks
     c.take<double>(3 * (n + 1));                  // witnesses
     c.take<uint8_t>(n + 1);                       // status
-    c.take<int64_t>((size_t)RGRID * 2 * (n + 1)); // per work-group lists
+    c.take<int64_t>((size_t)RGRID * 3 * (n + 1)); // per work-group lists
     c.take<int32_t>((size_t)RGRID * RW * flist_cap(n)); // per wave cap lists
     return c.used + 1024;
 }
@@ -174,7 +174,7 @@ size_t repair_ws(int64_t n, int64_t m, const sdfi_options &) {
     c.take<double>(n + 1);                        // their radii
     c.take<uint8_t>(n + 1);                       // their kinds
     c.take<double>(3 * (n + m + 1));              // contact points
-    c.take<int64_t>((size_t)RGRID * 2 * (n + 1)); // per work-group lists
+    c.take<int64_t>((size_t)RGRID * 3 * (n + 1)); // per work-group lists
     c.take<int32_t>((size_t)RGRID * RW * flist_cap(n)); // per wave cap lists
     return c.used + 4096;
 }
@@ -201,7 +201,7 @@ extern "C" sdfi_status sdfi_min_valid_radius(const double *samples, int64_t n, c
     char *chk = c.take<char>(check_ws(0));
     double *W = c.take<double>(3 * (n + 1));
     uint8_t *wst = c.take<uint8_t>(n + 1);
-    int64_t *lists = c.take<int64_t>((size_t)RGRID * 2 * (n + 1));
+    int64_t *lists = c.take<int64_t>((size_t)RGRID * 3 * (n + 1));
     int32_t *flists = c.take<int32_t>((size_t)RGRID * RW * flist_cap(n));
     s = validate_inputs(samples, n, queries, m, nullptr, 0, 0, true, chk, check_ws(0), o, st);
     if (s != SDFI_OK) return s;
@@ -239,7 +239,7 @@ extern "C" sdfi_status sdfi_repair(const double *samples, int64_t n, const doubl
     double *rval = c.take<double>(n + 1);
     uint8_t *rkind = c.take<uint8_t>(n + 1);
     double *contact = c.take<double>(3 * (n + m + 1));
-    int64_t *lists = c.take<int64_t>((size_t)RGRID * 2 * (n + 1));
+    int64_t *lists = c.take<int64_t>((size_t)RGRID * 3 * (n + 1));
     int32_t *flists = c.take<int32_t>((size_t)RGRID * RW * flist_cap(n));
     s = validate_inputs(samples, n, queries, m, nullptr, 0, 0, true, chk, check_ws(0), o, st);
     if (s != SDFI_OK) return s;
