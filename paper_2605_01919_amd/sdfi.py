@@ -267,7 +267,9 @@ def greedy(samples, queries, order=None, grid=0, certify=False, input_check=Fals
 
 
 def greedy_batched(instances, certify=False, block_size=0, groups=0):
-    """instances: list of (samples (n_i,4), queries (8 n_i,3), grid_i) GPU tensors."""
+    """instances: list of (samples (n_i,4), queries (8 n_i,3), grid_i) GPU tensors.
+    groups: most work-groups per instance (0: 16); the resident groups are shared
+    out by pair count when there are at least two per instance."""
     soff = [0]
     qoff = [0]
     for s, q, g in instances:

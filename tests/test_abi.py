@@ -86,6 +86,15 @@ def test_counters_and_block_size_on_host():
     o = sdfi.options(block_size=1024)
     assert L.sdfi_workspace_size(4, 5000, 40000, ctypes.byref(o), ctypes.byref(size)) == 1
     assert b"block_size" in L.sdfi_last_error()
+    # a batched launch adds a fixed amount per instance
+    o = sdfi.options()
+    assert L.sdfi_workspace_size(8, 0, 0, ctypes.byref(o), ctypes.byref(size)) == 0 and size.value > 0
+    per_instance = size.value
+    o = sdfi.options(groups=32)
+    assert L.sdfi_workspace_size(8, 0, 0, ctypes.byref(o), ctypes.byref(size)) == 0 and size.value > per_instance
+    o = sdfi.options(groups=-1)
+    assert L.sdfi_workspace_size(8, 0, 0, ctypes.byref(o), ctypes.byref(size)) == 1
+    assert b"groups" in L.sdfi_last_error()
     # the documented flags pass, any other bit is refused
     o = sdfi.options(flags=sdfi.OPT_CERTIFY | sdfi.OPT_INPUT_CHECK | sdfi.OPT_EXHAUSTIVE)
     assert L.sdfi_workspace_size(4, 5000, 40000, ctypes.byref(o), ctypes.byref(size)) == 0
