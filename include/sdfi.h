@@ -112,7 +112,10 @@ typedef struct {
                               keeps resident); a batch shares the resident groups out
                               in proportion to each instance's pair count when there
                               are at least two per instance, else runs one group per
-                              instance. */
+                              instance.  Teams need every group resident at once: other
+                              kernels running on the device meanwhile can delay them
+                              (a team that waits past its bound fails with
+                              SDFI_ERR_DEVICE). */
 } sdfi_options;
 
 typedef struct {

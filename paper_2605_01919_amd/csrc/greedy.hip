@@ -685,7 +685,16 @@ int greedy_waves(const sdfi_options &o, int ninst = 1) {
 // device keeps resident (a cooperative launch needs every group resident).
 constexpr int TEAM_DEFAULT = 16;
 int team_request(const sdfi_options &o) { return o.groups > 0 ? o.groups : TEAM_DEFAULT; }
+
+// whether the current device takes cooperative launches (teams need them)
+bool cooperative_ok() {
+    int dev = 0, on = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    return hipDeviceGetAttribute(&on, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess && on != 0;
+}
+
 int team_groups(const sdfi_options &o, int nw) {
+    if (!cooperative_ok()) return 1;
     const int slots = resident_groups(nw);
     return std::max(1, std::min(team_request(o), slots));
 }
@@ -805,7 +814,7 @@ static sdfi_status greedy_common(int ninst, const int64_t *soff, const int64_t *
         const int cap = team_request(o);
         if (ninst == 1) {
             G[0] = team_groups(o, nw);
-        } else if (cap > 1 && slots >= 2 * ninst) {
+        } else if (cap > 1 && slots >= 2 * ninst && cooperative_ok()) {
             const int total = std::min<int64_t>(slots, (int64_t)cap * ninst);
             double wsum = 0.0;
             std::vector<double> wk(ninst);
