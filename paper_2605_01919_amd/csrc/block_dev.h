@@ -617,7 +617,7 @@ __device__ __noinline__ double ray_bound(const double *q, int sigma, const doubl
 // 1 T, 2 D, 3 U, -1 nothing found, -2 a search hit its cap (no answer).  list: scratch of 2 (N + 1) entries;
 // kp/kid: per wave LDS scratch; flist: NW lists of fcap entries (global) for exhaustive searches.
 // candidates a wave of a team takes at a time (a group alone takes 16)
-constexpr int TEAM_PULL = 2;
+constexpr int TEAM_PULL = 1;
 
 // The candidate pulls of one minimum-radius pass, for every wave of the
 // calling work-group: candidates list[0..len) (ball rows of p4, list[0] the
