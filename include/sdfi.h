@@ -295,7 +295,13 @@ sdfi_status sdfi_greedy_interpolate(const double *samples, int64_t n, const doub
  * arrays; grids[b] is its input grid resolution (> 0; queries are its
  * (2 grids[b])^3 child cell centres and order_in is not taken).  Outputs are
  * concatenated like the queries; `active` ids are local to the instance.
- * Results equal num_instances calls of sdfi_greedy_interpolate.
+ * Results equal num_instances calls of sdfi_greedy_interpolate.  Each
+ * instance runs on one work-group or on a team of them (opt->groups), the
+ * largest instances first.  ws_bytes: at least
+ * sdfi_workspace_size(SDFI_OP_GREEDY, total samples + num_instances, total
+ * queries) + num_instances * sdfi_workspace_size(SDFI_OP_GREEDY_INSTANCE).
+ * Errors as for sdfi_greedy_interpolate, naming the instance; the report
+ * sums over instances.
  * sample_offsets, query_offsets, grids: host arrays.  Synchronises. */
 sdfi_status sdfi_greedy_interpolate_batched(int32_t num_instances, const int64_t *sample_offsets,
                                             const int64_t *query_offsets, const int32_t *grids,
